@@ -1,0 +1,258 @@
+/*
+ * shiro.h - C ABI of the per-rank, column-based (sparsity-aware) SpMM path.
+ *
+ * One rank p of P owns row panel A^(p,:) of a CSR matrix A (n_rows x n_cols)
+ * in a 1D row partition.  Its work, on one GPU:
+ *   1. partition    - take the panel and its column blocks A^(p,q)
+ *                     (Sec. 2.2; Table 1: M rows per panel, K columns per block);
+ *   2. select_rows  - Cols(A^(p,q)) for every q: the ascending unique column ids
+ *                     of each block, compacted by prefix sum (Table 1; Sec. 3.1,
+ *                     column-based scheme; Sec. 5.1 stage 1);
+ *   3. pack_B       - gather exactly those rows of B into one contiguous buffer,
+ *                     the payload of volume |Cols| * N * sz (Sec. 3.1 Eq. V_col;
+ *                     Sec. 5.1 stage 3);
+ *   4. spmm         - Y = A^(p,:) B over the packed rows, all blocks summed into
+ *                     the panel's rows (Sec. 2.1; Sec. 2.2 stages 3-4; Sec. 5.1
+ *                     stage 5);
+ *   5. spmm_backward- gradients of a loss through step 4: dB = A^T dY and
+ *                     dvals = (dY B^T) sampled at the nonzeros (the paper's GNN
+ *                     training, Sec. 7.6, needs them; it does not describe them).
+ *
+ * Conventions shared by every call
+ *  - Every call returns an int status: SHIRO_OK (0) or a negative SHIRO_ERR_*.
+ *    Nothing throws across this boundary.  shiro_last_error() returns a
+ *    thread-local text for the last failure of the calling thread.
+ *  - d_* arguments are device pointers owned by the caller (for example
+ *    allocated through PyTorch).  h_* arguments are host pointers.  The plan
+ *    object and the arrays inside it are owned by the library and released by
+ *    shiro_plan_destroy().
+ *  - stream is a hipStream_t (NULL = the legacy default stream).  All device
+ *    work is ordered on it.  Only shiro_partition, shiro_select_rows,
+ *    shiro_prepare and shiro_autotune synchronise the stream or allocate; the
+ *    per-call steps (pack_B, spmm, spmm_backward) neither allocate nor
+ *    synchronise once shiro_prepare has run for their (N, dtype), so they can be
+ *    captured into a HIP graph.
+ *  - Matrices are row-major with a leading dimension (elements between rows):
+ *    B is n_cols x N (ldb >= N), Bpacked is U x N, Y and dY are M x N, dB is
+ *    n_cols x N.  Leading dimensions and base pointers that are multiples of
+ *    16 bytes take the vector path; other values take a scalar path.
+ *  - Sizes: n_rows, n_cols < 2^31; panel nonzeros < 2^31; all row * N address
+ *    arithmetic is 64-bit.
+ *  - The CSR is canonical: row_ptr non-decreasing from 0 to nnz, columns in
+ *    [0, n_cols), strictly ascending inside each row.  It is verified on the
+ *    device when SHIRO_CHECK_CSR is passed or the environment variable
+ *    SHIRO_CHECK=1 is set (SHIRO_ERR_BAD_CSR on violation).  Without the check
+ *    a malformed CSR gives unspecified results and may read out of bounds, so
+ *    callers with untrusted input should pass the flag.
+ *  - Determinism: every output is bitwise reproducible from run to run for a
+ *    fixed plan and tuning; the default paths use no floating-point atomics.
+ *  - A plan holds work buffers shared by its calls: calls on one plan must be
+ *    ordered (one stream, or explicit events); concurrent calls on one plan
+ *    race.  Different plans are independent.
+ */
+#ifndef SHIRO_H
+#define SHIRO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define SHIRO_API __attribute__((visibility("default")))
+#else
+#define SHIRO_API
+#endif
+
+/* hipStream_t without requiring the HIP headers. */
+typedef struct ihipStream_t* shiro_stream_t;
+
+/* Opaque per-rank plan: the panel's pattern, its selection and derived
+ * structures (work lists, transposed pattern, tuning).  Pattern-only: values
+ * are passed to each compute call, so a plan is reused while the sparsity
+ * pattern is unchanged (the paper reuses its offline analysis the same way,
+ * Sec. 5.1 and Sec. 5.3). */
+typedef struct shiro_plan_s* shiro_plan;
+
+typedef enum {
+  SHIRO_F32 = 0,  /* IEEE binary32 */
+  SHIRO_BF16 = 1  /* bfloat16 storage; arithmetic is float32, stores round to nearest even */
+} shiro_dtype;
+
+enum {
+  SHIRO_OK = 0,
+  SHIRO_ERR_INVALID_ARG = -1,   /* null pointer, bad size, p outside [0,P), ... */
+  SHIRO_ERR_BAD_CSR = -2,       /* CSR check failed (check mode only)           */
+  SHIRO_ERR_OOM = -3,           /* device allocation failed                     */
+  SHIRO_ERR_HIP = -4,           /* a HIP runtime call failed                    */
+  SHIRO_ERR_UNSUPPORTED = -5,   /* dtype pair or size outside what is built     */
+  SHIRO_ERR_NOT_READY = -6,     /* call out of order (e.g. pack before select)  */
+  SHIRO_ERR_CAPTURING = -7      /* would allocate/synchronise during capture    */
+};
+
+/* shiro_partition flags */
+#define SHIRO_CHECK_CSR 1u
+
+/* shiro_spmm modes */
+#define SHIRO_MODE_BATCHED 0u   /* all column blocks in one persistent launch, row-merged */
+#define SHIRO_MODE_PER_BLOCK 1u /* one launch per column block, summed in block order     */
+
+/* shiro_prepare / shiro_autotune operation mask */
+#define SHIRO_OP_SPMM 1u
+#define SHIRO_OP_BACKWARD 2u
+#define SHIRO_OP_PER_BLOCK 4u
+
+typedef struct {
+  int64_t n_rows, n_cols; /* global matrix shape                              */
+  int32_t P, p;           /* partition and this rank                          */
+  int64_t M, K;           /* ceil(n_rows/P) rows per panel, ceil(n_cols/P) cols per block */
+  int64_t row_begin;      /* first global row of the panel                    */
+  int64_t rows;           /* rows in this panel (M, or fewer for the last)    */
+  int64_t nz_begin;       /* index of the panel's first nonzero in the CSR    */
+  int64_t nnz;            /* nonzeros in the panel                            */
+  int64_t U;              /* sum_q |Cols(A^(p,q))|, -1 before select_rows     */
+} shiro_plan_info_t;
+
+/* Tuning knobs of one kernel family (spmm, transposed spmm or sddmm). */
+typedef struct {
+  int32_t chunk;     /* merge-path items (rows + nonzeros) per wavefront       */
+  int32_t lanes;     /* lanes sharing one dense row: 8, 16, 32 or 64 (tile width = lanes * 16 bytes) */
+  int32_t unroll;    /* nonzeros in flight per lane group: 1, 2 or 4           */
+  int32_t hot_rows;  /* dense rows staged in LDS per workgroup (0 = off)       */
+  int32_t xcd_remap; /* 1: give each XCD a contiguous range of work            */
+  int32_t wg_per_cu; /* persistent grid: workgroups per compute unit           */
+} shiro_tuning_t;
+
+#define SHIRO_KERNEL_SPMM 0
+#define SHIRO_KERNEL_SPMM_T 1
+#define SHIRO_KERNEL_SDDMM 2
+
+/* Library version, 10000*major + 100*minor + patch. */
+SHIRO_API int shiro_version(void);
+
+/* Text of the calling thread's last error ("" if none).  Valid until the
+ * thread's next failing call. */
+SHIRO_API const char* shiro_last_error(void);
+
+/* Build the plan of rank p (Sec. 2.2; Table 1).
+ *   n_rows, n_cols: shape of A; nnz = d_row_ptr[n_rows].
+ *   d_row_ptr: device int64[n_rows + 1]; d_col: device int32[nnz].  Only the
+ *     panel's rows [p*M, min(n_rows,(p+1)*M)) and their nonzeros are read; the
+ *     plan copies what it needs, so the caller may free them afterwards.
+ *   P >= 1 processes, 0 <= p < P.  Panels and column blocks are contiguous,
+ *     M = ceil(n_rows/P) rows and K = ceil(n_cols/P) columns; the last ones
+ *     may be shorter (or empty).
+ *   flags: SHIRO_CHECK_CSR validates the panel on the device first.
+ * Synchronises the stream (reads the panel's nonzero range).  Errors:
+ * INVALID_ARG, BAD_CSR, OOM, HIP, UNSUPPORTED (panel nnz >= 2^31). */
+SHIRO_API int shiro_partition(int64_t n_rows, int64_t n_cols, int64_t nnz,
+                              const int64_t* d_row_ptr, const int32_t* d_col, int32_t P,
+                              int32_t p, uint32_t flags, shiro_stream_t stream,
+                              shiro_plan* out_plan);
+
+SHIRO_API int shiro_plan_info(shiro_plan plan, shiro_plan_info_t* h_info);
+
+/* Nonzeros of the panel in each column block, written to device int64[P]. */
+SHIRO_API int shiro_block_nnz(shiro_plan plan, int64_t* d_block_nnz, shiro_stream_t stream);
+
+/* Cols(A^(p,q)) for every block q (Table 1; Sec. 3.1; Sec. 5.1 stage 1).
+ * Marks the column ids present in the panel, prefix-sums the marks and
+ * compacts them, so that the plan holds
+ *   unique_cols int32[U]: Cols_0, Cols_1, ... each ascending (global ids);
+ *   block_off  int64[P+1]: block q's ids are unique_cols[block_off[q] ..
+ *              block_off[q+1]);
+ *   colmap     int32[nnz]: packed position of each panel nonzero's column,
+ *              so unique_cols[colmap[k]] == col[k].
+ * Writes U to *h_U_total and |Cols_q| to h_U_per_block[q] (nullable, P
+ * entries).  Synchronises the stream to return U.  Idempotent. */
+SHIRO_API int shiro_select_rows(shiro_plan plan, shiro_stream_t stream, int64_t* h_U_total,
+                                int64_t* h_U_per_block);
+
+/* Device views of the selection (owned by the plan; valid until destroy).
+ * Any output pointer may be NULL.  NOT_READY before select_rows. */
+SHIRO_API int shiro_plan_selection(shiro_plan plan, const int32_t** d_unique_cols,
+                                   const int64_t** d_block_off, const int32_t** d_colmap);
+
+/* Copy the selection into caller-owned device buffers (any may be NULL):
+ * d_unique_cols int32[U], d_block_off int64[P+1], d_colmap int32[nnz].
+ * Stream-ordered.  NOT_READY before select_rows. */
+SHIRO_API int shiro_copy_selection(shiro_plan plan, int32_t* d_unique_cols, int64_t* d_block_off,
+                                   int32_t* d_colmap, shiro_stream_t stream);
+
+/* Pack (Sec. 3.1 Eq. V_col; Sec. 5.1 stage 3):
+ *   Bpacked[u, 0:N] = B[unique_cols[u], 0:N] for u in [0, U), a bit-exact copy.
+ * d_B: n_cols x N of dtype dt with leading dimension ldb >= N; d_Bpacked:
+ * U x N with ldp >= N, same dtype, must not overlap d_B.  NOT_READY before
+ * select_rows. */
+SHIRO_API int shiro_pack_B(shiro_plan plan, const void* d_B, int64_t ldb, int32_t N,
+                           shiro_dtype dt, void* d_Bpacked, int64_t ldp,
+                           shiro_stream_t stream);
+
+/* Local SpMM with aggregation over the column blocks (Sec. 2.1; Sec. 2.2
+ * stages 3-4; Sec. 5.1 stage 5):
+ *   Y[i, :] = sum_q sum_{k in row i of block q} vals[k] * Bpacked[colmap[k], :]
+ * for the panel's rows i in [0, rows).  Y is overwritten (empty rows get 0).
+ * d_vals: float32 values indexed like d_col of shiro_partition (global nonzero
+ * index; the plan offsets by nz_begin).  Products and sums are float32; the
+ * sum of each output element is taken in a fixed order.
+ * Supported (in_dt -> out_dt): F32->F32, BF16->F32, BF16->BF16.
+ * mode: SHIRO_MODE_BATCHED (one persistent launch over all blocks) or
+ * SHIRO_MODE_PER_BLOCK (one launch per block, accumulated in block order).
+ * NOT_READY before select_rows; CAPTURING if capture is active and the
+ * structures for (N, dtype, mode) were not prepared. */
+SHIRO_API int shiro_spmm(shiro_plan plan, const float* d_vals, const void* d_Bpacked,
+                         int64_t ldp, int32_t N, shiro_dtype in_dt, void* d_Y, int64_t ldy,
+                         shiro_dtype out_dt, uint32_t mode, shiro_stream_t stream);
+
+/* Backward of Y = A Bpacked for a loss with upstream gradient dY (M x N):
+ *   dBpacked = A^T dY                       (U x N, overwritten; nullable)
+ *   dB[unique_cols[u], :] += dBpacked[u, :] (n_cols x N, read-modify-write into
+ *                                            the caller's buffer; nullable)
+ *   dvals[k] = dY[i(k), :] . Bpacked[colmap[k], :]  (float32 per nonzero,
+ *                                            indexed like d_vals; nullable)
+ * A^T is applied through a transposed pattern built once per plan by a stable
+ * radix sort (no atomics).  dt applies to dY, Bpacked, dBpacked and dB
+ * (F32 or BF16; arithmetic float32).  NOT_READY before select_rows. */
+SHIRO_API int shiro_spmm_backward(shiro_plan plan, const float* d_vals, const void* d_dY,
+                                  int64_t lddy, const void* d_Bpacked, int64_t ldp, int32_t N,
+                                  shiro_dtype dt, void* d_dBpacked, int64_t lddbp, void* d_dB,
+                                  int64_t lddb, float* d_dvals, shiro_stream_t stream);
+
+/* Build everything the per-call steps need for (N, dtype, ops) - work lists,
+ * transposed pattern, carry buffers - so later calls neither allocate nor
+ * synchronise (required before graph capture).  Synchronises the stream. */
+SHIRO_API int shiro_prepare(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t ops,
+                            shiro_stream_t stream);
+
+/* Time candidate tunings of the kernels in `ops` on scratch data of the
+ * plan's shape at width N and keep the fastest per kernel in the plan.  If
+ * the environment variable SHIRO_TUNE_CACHE names a file, results are read
+ * from and appended to it (one line per key).  Allocates and synchronises. */
+SHIRO_API int shiro_autotune(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t ops,
+                             shiro_stream_t stream);
+
+/* Read or override the tuning the plan uses for one kernel family
+ * (SHIRO_KERNEL_*) at width N.  set validates the knobs (INVALID_ARG). */
+SHIRO_API int shiro_get_tuning(shiro_plan plan, int32_t kernel, int32_t N, shiro_dtype dt,
+                               shiro_tuning_t* h_tuning);
+SHIRO_API int shiro_set_tuning(shiro_plan plan, int32_t kernel, int32_t N, shiro_dtype dt,
+                               const shiro_tuning_t* h_tuning);
+
+/* HIP graph capture of any sequence of pack_B / spmm / spmm_backward calls on
+ * `stream`: begin, issue the calls, end; the instantiated graph is kept in the
+ * plan under *h_graph_id and replayed by shiro_graph_launch.  Pointers and
+ * sizes are frozen at capture.  Run shiro_prepare first. */
+SHIRO_API int shiro_graph_begin(shiro_plan plan, shiro_stream_t stream);
+SHIRO_API int shiro_graph_end(shiro_plan plan, shiro_stream_t stream, int32_t* h_graph_id);
+SHIRO_API int shiro_graph_launch(shiro_plan plan, int32_t graph_id, shiro_stream_t stream);
+
+/* Release the plan and everything it owns (synchronises the device first).
+ * NULL is accepted. */
+SHIRO_API int shiro_plan_destroy(shiro_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHIRO_H */

@@ -1,0 +1,295 @@
+"""Per-rank, column-based (sparsity-aware) SpMM of SHIRO on MI355X (gfx950).
+
+Thin Python binding over libshiro.so (C ABI in include/shiro.h).  The
+functions keep the C names without the prefix: partition, select_rows,
+pack_B, spmm, spmm_backward (plus prepare, autotune, tuning and graph
+capture).  PyTorch provides device memory and the stream; every step of
+the path runs in the library's HIP kernels.  There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import contextlib
+import ctypes
+from typing import Optional, Tuple
+
+import torch
+
+from . import _lib
+from ._lib import ShiroError, Tuning  # noqa: F401
+
+__all__ = [
+    "Plan",
+    "ShiroError",
+    "partition",
+    "select_rows",
+    "selection",
+    "block_nnz",
+    "pack_B",
+    "spmm",
+    "spmm_backward",
+    "prepare",
+    "autotune",
+    "get_tuning",
+    "set_tuning",
+    "ShiroSpMM",
+    "shiro_spmm",
+    "version",
+]
+
+_DT = {torch.float32: _lib.F32, torch.bfloat16: _lib.BF16}
+_KERNELS = {"spmm": _lib.KERNEL_SPMM, "spmm_t": _lib.KERNEL_SPMM_T, "sddmm": _lib.KERNEL_SDDMM}
+
+
+def _L():
+    return _lib.load()
+
+
+def _stream(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _dt(t: torch.dtype) -> int:
+    if t not in _DT:
+        raise TypeError(f"unsupported dtype {t}: float32 or bfloat16")
+    return _DT[t]
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _ld(t: torch.Tensor) -> int:
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("dense operands must be 2-D with unit column stride (row-major)")
+    return t.stride(0)
+
+
+def _dev(t: torch.Tensor):
+    if not t.is_cuda:
+        raise ValueError("operands must live on the GPU")
+
+
+def version() -> int:
+    return int(_L().shiro_version())
+
+
+class Plan:
+    """Library-owned plan of rank p's panel (freed when garbage collected)."""
+
+    def __init__(self, handle: int, device: torch.device):
+        self._h = ctypes.c_void_p(handle)
+        self.device = device
+        self._graphs = []
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        inf = _lib.PlanInfo()
+        _lib.check(_L().shiro_plan_info(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in inf._fields_}
+
+    def __getattr__(self, name):
+        if name in ("n_rows", "n_cols", "P", "p", "M", "K", "row_begin", "rows", "nz_begin", "nnz", "U"):
+            return self.info()[name]
+        raise AttributeError(name)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _L().shiro_plan_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # HIP graph capture of pack_B / spmm / spmm_backward calls
+    @contextlib.contextmanager
+    def capture(self, stream: torch.cuda.Stream):
+        """Record the library calls issued on `stream` inside the block.
+
+        Yields a list that receives the graph id once capture ends."""
+        holder = []
+        _lib.check(_L().shiro_graph_begin(self._h, ctypes.c_void_p(stream.cuda_stream)))
+        try:
+            with torch.cuda.stream(stream):
+                yield holder
+        finally:
+            gid = ctypes.c_int32(-1)
+            _lib.check(_L().shiro_graph_end(self._h, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(gid)))
+            holder.append(gid.value)
+
+    def replay(self, graph_id: int, stream=None):
+        _lib.check(_L().shiro_graph_launch(self._h, int(graph_id), ctypes.c_void_p(_stream(stream))))
+
+
+def partition(row_ptr: torch.Tensor, col: torch.Tensor, n_rows: int, n_cols: int, P: int, p: int,
+              check: bool = False, stream=None) -> Plan:
+    """Plan of panel p of P for the CSR (row_ptr int64[n_rows+1], col int32[nnz])."""
+    _dev(row_ptr)
+    if row_ptr.dtype != torch.int64 or col.dtype != torch.int32:
+        raise TypeError("row_ptr must be int64 and col int32")
+    if row_ptr.numel() != n_rows + 1:
+        raise ValueError("row_ptr must have n_rows + 1 entries")
+    h = ctypes.c_void_p()
+    nnz = col.numel()
+    _lib.check(_L().shiro_partition(int(n_rows), int(n_cols), int(nnz), _ptr(row_ptr.contiguous()),
+                                    _ptr(col.contiguous()) if nnz else None, int(P), int(p),
+                                    _lib.CHECK_CSR if check else 0, ctypes.c_void_p(_stream(stream)),
+                                    ctypes.byref(h)))
+    return Plan(h.value, row_ptr.device)
+
+
+def select_rows(plan: Plan, stream=None) -> Tuple[int, list]:
+    """Run the selection; returns (U, [|Cols_q| for q in range(P)])."""
+    P = plan.info()["P"]
+    U = ctypes.c_int64()
+    per = (ctypes.c_int64 * P)()
+    _lib.check(_L().shiro_select_rows(plan.handle, ctypes.c_void_p(_stream(stream)), ctypes.byref(U), per))
+    return U.value, list(per)
+
+
+def selection(plan: Plan, stream=None):
+    """Copies of (unique_cols int32[U], block_off int64[P+1], colmap int32[nnz])."""
+    inf = plan.info()
+    if inf["U"] < 0:
+        raise ShiroError(-6, "select_rows has not run")
+    dev = plan.device
+    uc = torch.empty(inf["U"], dtype=torch.int32, device=dev)
+    off = torch.empty(inf["P"] + 1, dtype=torch.int64, device=dev)
+    cm = torch.empty(inf["nnz"], dtype=torch.int32, device=dev)
+    _lib.check(_L().shiro_copy_selection(plan.handle, _ptr(uc), _ptr(off), _ptr(cm), ctypes.c_void_p(_stream(stream))))
+    return uc, off, cm
+
+
+def block_nnz(plan: Plan, stream=None) -> torch.Tensor:
+    out = torch.empty(plan.info()["P"], dtype=torch.int64, device=plan.device)
+    _lib.check(_L().shiro_block_nnz(plan.handle, _ptr(out), ctypes.c_void_p(_stream(stream))))
+    return out
+
+
+def pack_B(plan: Plan, B: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Bpacked[u] = B[unique_cols[u]] (bit-exact), shape U x N."""
+    _dev(B)
+    U = plan.info()["U"]
+    N = B.shape[1]
+    if out is None:
+        out = torch.empty(U, N, dtype=B.dtype, device=B.device)
+    if out.dtype != B.dtype or out.shape[0] < U or out.shape[1] != N:
+        raise ValueError("out must be U x N with B's dtype")
+    _lib.check(_L().shiro_pack_B(plan.handle, _ptr(B), _ld(B), N, _dt(B.dtype), _ptr(out), _ld(out),
+                                 ctypes.c_void_p(_stream(stream))))
+    return out
+
+
+def spmm(plan: Plan, vals: torch.Tensor, Bpacked: torch.Tensor, out: Optional[torch.Tensor] = None,
+         out_dtype: Optional[torch.dtype] = None, mode: str = "batched", stream=None) -> torch.Tensor:
+    """Y = A^(p,:) Bpacked (rows x N); vals is the CSR's float32 value array."""
+    _dev(Bpacked)
+    if vals.dtype != torch.float32:
+        raise TypeError("vals must be float32")
+    rows = plan.info()["rows"]
+    N = Bpacked.shape[1]
+    out_dtype = out_dtype or Bpacked.dtype
+    if out is None:
+        out = torch.empty(rows, N, dtype=out_dtype, device=Bpacked.device)
+    m = {"batched": _lib.MODE_BATCHED, "per_block": _lib.MODE_PER_BLOCK}[mode]
+    _lib.check(_L().shiro_spmm(plan.handle, _ptr(vals), _ptr(Bpacked), _ld(Bpacked), N, _dt(Bpacked.dtype),
+                               _ptr(out), _ld(out), _dt(out.dtype), m, ctypes.c_void_p(_stream(stream))))
+    return out
+
+
+def spmm_backward(plan: Plan, vals: torch.Tensor, dY: torch.Tensor, Bpacked: Optional[torch.Tensor],
+                  dBpacked: Optional[torch.Tensor] = None, dB: Optional[torch.Tensor] = None,
+                  dvals: Optional[torch.Tensor] = None, stream=None):
+    """dBpacked = A^T dY (overwrite), dB[unique_cols] += dBpacked, dvals = SDDMM(dY, Bpacked).
+
+    Pass the output tensors to compute; None skips an output."""
+    _dev(dY)
+    N = dY.shape[1]
+    dt = _dt(dY.dtype)
+    for t in (Bpacked, dBpacked, dB):
+        if t is not None and t.dtype != dY.dtype:
+            raise TypeError("dY, Bpacked, dBpacked and dB share one dtype")
+    _lib.check(_L().shiro_spmm_backward(
+        plan.handle, _ptr(vals), _ptr(dY), _ld(dY), _ptr(Bpacked), _ld(Bpacked) if Bpacked is not None else N,
+        N, dt, _ptr(dBpacked), _ld(dBpacked) if dBpacked is not None else N, _ptr(dB),
+        _ld(dB) if dB is not None else N, _ptr(dvals), ctypes.c_void_p(_stream(stream))))
+    return dBpacked, dB, dvals
+
+
+_OPS = {"spmm": _lib.OP_SPMM, "backward": _lib.OP_BACKWARD, "per_block": _lib.OP_PER_BLOCK}
+
+
+def _ops(ops) -> int:
+    if isinstance(ops, int):
+        return ops
+    v = 0
+    for o in ops:
+        v |= _OPS[o]
+    return v
+
+
+def prepare(plan: Plan, N: int, dtype=torch.float32, ops=("spmm", "backward"), stream=None):
+    _lib.check(_L().shiro_prepare(plan.handle, int(N), _dt(dtype), _ops(ops), ctypes.c_void_p(_stream(stream))))
+
+
+def autotune(plan: Plan, N: int, dtype=torch.float32, ops=("spmm", "backward"), stream=None):
+    _lib.check(_L().shiro_autotune(plan.handle, int(N), _dt(dtype), _ops(ops), ctypes.c_void_p(_stream(stream))))
+
+
+def get_tuning(plan: Plan, kernel: str, N: int, dtype=torch.float32) -> dict:
+    t = Tuning()
+    _lib.check(_L().shiro_get_tuning(plan.handle, _KERNELS[kernel], int(N), _dt(dtype), ctypes.byref(t)))
+    return t.as_dict()
+
+
+def set_tuning(plan: Plan, kernel: str, N: int, dtype=torch.float32, **knobs):
+    cur = get_tuning(plan, kernel, N, dtype)
+    cur.update(knobs)
+    t = Tuning(**cur)
+    _lib.check(_L().shiro_set_tuning(plan.handle, _KERNELS[kernel], int(N), _dt(dtype), ctypes.byref(t)))
+
+
+# ---------------------------------------------------------------------------
+# autograd: Y = A B with gradients for the values and for B
+# ---------------------------------------------------------------------------
+class ShiroSpMM(torch.autograd.Function):
+    """Y = A^(p,:) B through select/pack/spmm; backward through spmm_backward.
+
+    Inputs: vals (float32, the CSR's value array), B (n_cols x N, float32 or
+    bfloat16).  The plan must have run select_rows.  Gradients: dvals (float32,
+    nonzero entries of the panel only) and dB (B's dtype, rows outside
+    Cols(panel) are zero).
+    """
+
+    @staticmethod
+    def forward(ctx, vals, B, plan, out_dtype=None):
+        Bp = pack_B(plan, B)
+        Y = spmm(plan, vals, Bp, out_dtype=out_dtype)
+        ctx.plan = plan
+        ctx.save_for_backward(vals, Bp)
+        ctx.B_shape = B.shape
+        ctx.B_dtype = B.dtype
+        return Y
+
+    @staticmethod
+    def backward(ctx, dY):
+        vals, Bp = ctx.saved_tensors
+        plan = ctx.plan
+        dY = dY.to(ctx.B_dtype).contiguous()
+        dvals = dB = None
+        if ctx.needs_input_grad[0]:
+            dvals = torch.zeros_like(vals)
+        if ctx.needs_input_grad[1]:
+            dB = torch.zeros(ctx.B_shape, dtype=ctx.B_dtype, device=dY.device)
+        spmm_backward(plan, vals, dY, Bp, None, dB, dvals)
+        return dvals, dB, None, None
+
+
+def shiro_spmm(plan: Plan, vals: torch.Tensor, B: torch.Tensor, out_dtype=None) -> torch.Tensor:
+    return ShiroSpMM.apply(vals, B, plan, out_dtype)

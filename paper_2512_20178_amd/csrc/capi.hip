@@ -1,0 +1,637 @@
+// C ABI of the per-rank path: argument validation, plan lifecycle, tuning,
+// autotuner and HIP graph capture.  Kernels live in select/sort/spmm.hip.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+
+namespace shiro {
+
+static thread_local std::string g_last_error;
+
+int set_error(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int dev_alloc(void** p, int64_t bytes) {
+  *p = nullptr;
+  if (bytes <= 0) bytes = 1;
+  hipError_t e = hipMalloc(p, (size_t)bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return set_error(e == hipErrorOutOfMemory ? SHIRO_ERR_OOM : SHIRO_ERR_HIP,
+                     "device allocation of " + std::to_string(bytes) + " bytes failed: " +
+                         hipGetErrorString(e));
+  }
+  return SHIRO_OK;
+}
+
+void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+bool stream_capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+  return st == hipStreamCaptureStatusActive;
+}
+
+int ensure_scratch(shiro_plan plan, int64_t bytes) {
+  if (plan->scratch_bytes >= bytes) return SHIRO_OK;
+  SHIRO_HIP(hipDeviceSynchronize());  // earlier setup kernels may still use it
+  dev_free(plan->scratch);
+  plan->scratch = nullptr;
+  plan->scratch_bytes = 0;
+  SHIRO_TRY(dev_alloc(&plan->scratch, bytes));
+  plan->scratch_bytes = bytes;
+  return SHIRO_OK;
+}
+
+int ensure_rows_work(shiro_plan plan, int32_t chunk, bool allocate, hipStream_t s,
+                     const WorkList** out) {
+  auto it = plan->rows_work.find(chunk);
+  if (it == plan->rows_work.end()) {
+    if (!allocate)
+      return set_error(SHIRO_ERR_CAPTURING,
+                       "work list for chunk " + std::to_string(chunk) + " not prepared before capture");
+    WorkList wl;
+    SHIRO_TRY(build_worklist(plan->row_ptr, plan->rows, plan->nnz, chunk, &wl, s));
+    it = plan->rows_work.emplace(chunk, wl).first;
+  }
+  *out = &it->second;
+  return SHIRO_OK;
+}
+
+int ensure_cols_work(shiro_plan plan, int32_t chunk, bool allocate, hipStream_t s,
+                     const WorkList** out) {
+  auto it = plan->cols_work.find(chunk);
+  if (it == plan->cols_work.end()) {
+    if (!allocate)
+      return set_error(SHIRO_ERR_CAPTURING,
+                       "transposed work list for chunk " + std::to_string(chunk) + " not prepared before capture");
+    WorkList wl;
+    SHIRO_TRY(build_worklist(plan->tr.ptr, plan->U, plan->nnz, chunk, &wl, s));
+    it = plan->cols_work.emplace(chunk, wl).first;
+  }
+  *out = &it->second;
+  return SHIRO_OK;
+}
+
+int ensure_carry(shiro_plan plan, int64_t elems, bool allocate) {
+  if (plan->carry_elems >= elems) return SHIRO_OK;
+  if (!allocate) return set_error(SHIRO_ERR_CAPTURING, "carry buffer not prepared before capture");
+  SHIRO_HIP(hipDeviceSynchronize());
+  dev_free(plan->carry);
+  plan->carry = nullptr;
+  plan->carry_elems = 0;
+  SHIRO_TRY(dev_alloc_n(&plan->carry, elems));
+  plan->carry_elems = elems;
+  return SHIRO_OK;
+}
+
+shiro_tuning_t default_tuning(int kernel, int32_t, shiro_dtype) {
+  shiro_tuning_t t;
+  t.chunk = kernel == SHIRO_KERNEL_SDDMM ? 512 : 256;
+  t.lanes = 64;
+  t.unroll = 2;
+  t.hot_rows = 0;
+  t.xcd_remap = 0;
+  t.wg_per_cu = 8;
+  return t;
+}
+
+int validate_tuning(int kernel, int32_t, shiro_dtype, const shiro_tuning_t& t) {
+  if (kernel < 0 || kernel > 2) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: unknown kernel family");
+  if (t.chunk < 16 || t.chunk > (1 << 22)) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: chunk outside [16, 2^22]");
+  if (t.lanes != 8 && t.lanes != 16 && t.lanes != 32 && t.lanes != 64)
+    return set_error(SHIRO_ERR_INVALID_ARG, "tuning: lanes must be 8, 16, 32 or 64");
+  if (t.unroll != 1 && t.unroll != 2 && t.unroll != 4)
+    return set_error(SHIRO_ERR_INVALID_ARG, "tuning: unroll must be 1, 2 or 4");
+  if (t.hot_rows != 0) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: hot_rows must be 0 in this build");
+  if (t.xcd_remap != 0 && t.xcd_remap != 1) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: xcd_remap must be 0 or 1");
+  if (t.wg_per_cu < 1 || t.wg_per_cu > 32) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: wg_per_cu outside [1, 32]");
+  return SHIRO_OK;
+}
+
+static shiro_tuning_t tuning_for(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt) {
+  auto it = plan->tuning.find(TuneKey{kernel, N, (int)dt});
+  if (it != plan->tuning.end()) return it->second;
+  return default_tuning(kernel, N, dt);
+}
+
+static bool env_check() {
+  const char* e = std::getenv("SHIRO_CHECK");
+  return e && e[0] == '1';
+}
+
+static bool valid_dt(shiro_dtype dt) { return dt == SHIRO_F32 || dt == SHIRO_BF16; }
+static int64_t dt_size(shiro_dtype dt) { return dt == SHIRO_F32 ? 4 : 2; }
+
+static void plan_free(shiro_plan plan) {
+  if (!plan) return;
+  (void)hipDeviceSynchronize();
+  for (auto& g : plan->graphs)
+    if (g) (void)hipGraphExecDestroy(g);
+  dev_free(plan->row_ptr);
+  dev_free(plan->col);
+  dev_free(plan->bitmap);
+  dev_free(plan->word_off);
+  dev_free(plan->unique_cols);
+  dev_free(plan->block_off);
+  dev_free(plan->colmap);
+  for (auto& kv : plan->rows_work) {
+    dev_free(kv.second.chunk_row);
+    dev_free(kv.second.chunk_nz);
+  }
+  for (auto& kv : plan->cols_work) {
+    dev_free(kv.second.chunk_row);
+    dev_free(kv.second.chunk_nz);
+  }
+  dev_free(plan->tr.ptr);
+  dev_free(plan->tr.row);
+  dev_free(plan->tr.perm);
+  dev_free(plan->seg.seg_row);
+  dev_free(plan->seg.seg_begin);
+  dev_free(plan->seg.seg_end);
+  dev_free(plan->carry);
+  dev_free(plan->scratch);
+  if (plan->h_pinned) (void)hipHostFree(plan->h_pinned);
+  delete plan;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+struct TuneBuffers {
+  void* Bp = nullptr;
+  void* Y = nullptr;
+  void* dY = nullptr;
+  void* dBp = nullptr;
+  float* vals = nullptr;
+  float* dvals = nullptr;
+  ~TuneBuffers() {
+    dev_free(Bp);
+    dev_free(Y);
+    dev_free(dY);
+    dev_free(dBp);
+    dev_free(vals);
+    dev_free(dvals);
+  }
+};
+
+static std::string tune_key(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt) {
+  hipDeviceProp_t prop;
+  std::string name = "gpu";
+  if (hipGetDeviceProperties(&prop, plan->device) == hipSuccess) name = prop.gcnArchName;
+  for (auto& ch : name)
+    if (ch == ' ' || ch == ':') ch = '_';
+  std::ostringstream os;
+  os << name << "|rows=" << plan->rows << "|nnz=" << plan->nnz << "|U=" << plan->U
+     << "|P=" << plan->P << "|N=" << N << "|dt=" << (int)dt << "|k=" << kernel;
+  return os.str();
+}
+
+static bool cache_lookup(const std::string& key, shiro_tuning_t* t) {
+  const char* path = std::getenv("SHIRO_TUNE_CACHE");
+  if (!path || !*path) return false;
+  std::ifstream f(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    std::istringstream is(line);
+    std::string k;
+    shiro_tuning_t c;
+    if (is >> k >> c.chunk >> c.lanes >> c.unroll >> c.hot_rows >> c.xcd_remap >> c.wg_per_cu) {
+      if (k == key) {
+        *t = c;
+        found = true;  // last entry wins
+      }
+    }
+  }
+  return found;
+}
+
+static void cache_store(const std::string& key, const shiro_tuning_t& t) {
+  const char* path = std::getenv("SHIRO_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::ofstream f(path, std::ios::app);
+  f << key << ' ' << t.chunk << ' ' << t.lanes << ' ' << t.unroll << ' ' << t.hot_rows << ' '
+    << t.xcd_remap << ' ' << t.wg_per_cu << '\n';
+}
+
+template <class F>
+static int time_candidate(hipStream_t s, F&& run, float* ms_out) {
+  hipEvent_t e0, e1;
+  SHIRO_HIP(hipEventCreate(&e0));
+  SHIRO_HIP(hipEventCreate(&e1));
+  int rc = run();  // warm-up (also builds work lists)
+  if (rc != SHIRO_OK) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+  }
+  float best = 1e30f;
+  for (int rep = 0; rep < 5 && rc == SHIRO_OK; ++rep) {
+    (void)hipEventRecord(e0, s);
+    rc = run();
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    best = std::min(best, ms);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms_out = best;
+  return rc;
+}
+
+static int tune_one(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt, TuneBuffers& b,
+                    hipStream_t s) {
+  const std::string key = tune_key(plan, kernel, N, dt);
+  shiro_tuning_t cached;
+  if (cache_lookup(key, &cached) && validate_tuning(kernel, N, dt, cached) == SHIRO_OK) {
+    plan->tuning[TuneKey{kernel, N, (int)dt}] = cached;
+    return SHIRO_OK;
+  }
+  auto run = [&](const shiro_tuning_t& t) -> int {
+    if (kernel == SHIRO_KERNEL_SPMM)
+      return launch_spmm(plan, t, b.vals, b.Bp, N, N, dt, b.Y, N, dt == SHIRO_F32 ? SHIRO_F32 : SHIRO_BF16, s);
+    if (kernel == SHIRO_KERNEL_SPMM_T)
+      return launch_spmm_t(plan, t, b.vals, b.dY, N, N, dt, b.dBp, N, nullptr, 0, s);
+    return launch_sddmm(plan, t, b.vals, b.dY, N, b.Bp, N, N, dt, b.dvals, s);
+  };
+  shiro_tuning_t best = default_tuning(kernel, N, dt);
+  float best_ms = 1e30f;
+  auto consider = [&](shiro_tuning_t t) -> int {
+    float ms;
+    int rc = time_candidate(s, [&] { return run(t); }, &ms);
+    if (rc != SHIRO_OK) return rc;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+    return SHIRO_OK;
+  };
+  // stage 1: work size and depth
+  for (int chunk : {128, 256, 512, 1024, 2048})
+    for (int unroll : {1, 2, 4}) {
+      shiro_tuning_t t = default_tuning(kernel, N, dt);
+      t.chunk = chunk;
+      t.unroll = unroll;
+      SHIRO_TRY(consider(t));
+    }
+  // stage 2: lane width, occupancy, XCD placement around the best
+  const shiro_tuning_t base = best;
+  for (int lanes : {64, 32, 16})
+    for (int wg : {4, 8, 16})
+      for (int xcd : {0, 1}) {
+        shiro_tuning_t t = base;
+        t.lanes = lanes;
+        t.wg_per_cu = wg;
+        t.xcd_remap = xcd;
+        SHIRO_TRY(consider(t));
+      }
+  plan->tuning[TuneKey{kernel, N, (int)dt}] = best;
+  cache_store(key, best);
+  return SHIRO_OK;
+}
+
+}  // namespace shiro
+
+using namespace shiro;
+
+// ===========================================================================
+// exported functions
+// ===========================================================================
+extern "C" {
+
+SHIRO_API int shiro_version(void) { return 10000; }
+
+SHIRO_API const char* shiro_last_error(void) { return g_last_error.c_str(); }
+
+SHIRO_API int shiro_partition(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t* d_row_ptr,
+                              const int32_t* d_col, int32_t P, int32_t p, uint32_t flags,
+                              shiro_stream_t stream, shiro_plan* out_plan) {
+  if (!out_plan) return set_error(SHIRO_ERR_INVALID_ARG, "partition: out_plan is NULL");
+  *out_plan = nullptr;
+  if (n_rows < 1 || n_cols < 1 || n_rows >= (1ll << 31) || n_cols >= (1ll << 31))
+    return set_error(SHIRO_ERR_INVALID_ARG, "partition: n_rows and n_cols must be in [1, 2^31)");
+  if (nnz < 0) return set_error(SHIRO_ERR_INVALID_ARG, "partition: nnz < 0");
+  if (!d_row_ptr) return set_error(SHIRO_ERR_INVALID_ARG, "partition: d_row_ptr is NULL");
+  if (nnz > 0 && !d_col) return set_error(SHIRO_ERR_INVALID_ARG, "partition: d_col is NULL");
+  if (P < 1) return set_error(SHIRO_ERR_INVALID_ARG, "partition: P < 1");
+  if (p < 0 || p >= P) return set_error(SHIRO_ERR_INVALID_ARG, "partition: p outside [0, P)");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (stream_capturing(s)) return set_error(SHIRO_ERR_CAPTURING, "partition: stream is capturing");
+
+  auto* plan = new shiro_plan_s();
+  auto fail = [&](int rc) {
+    plan_free(plan);
+    return rc;
+  };
+  if (hipGetDevice(&plan->device) != hipSuccess) return fail(set_error(SHIRO_ERR_HIP, "hipGetDevice failed"));
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, plan->device) == hipSuccess && prop.multiProcessorCount > 0)
+    plan->num_cus = prop.multiProcessorCount;
+  plan->n_rows = n_rows;
+  plan->n_cols = n_cols;
+  plan->P = P;
+  plan->p = p;
+  plan->M = ceil_div(n_rows, P);
+  plan->K = ceil_div(n_cols, P);
+  plan->row_begin = std::min<int64_t>((int64_t)p * plan->M, n_rows);
+  const int64_t row_end = std::min<int64_t>(plan->row_begin + plan->M, n_rows);
+  plan->rows = row_end - plan->row_begin;
+
+  if (hipHostMalloc((void**)&plan->h_pinned, (size_t)(P + 2) * 8, hipHostMallocDefault) != hipSuccess)
+    return fail(set_error(SHIRO_ERR_OOM, "partition: pinned host allocation failed"));
+  // panel nonzero range
+  if (hipMemcpyAsync(plan->h_pinned, d_row_ptr + plan->row_begin, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(plan->h_pinned + 1, d_row_ptr + row_end, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(set_error(SHIRO_ERR_HIP, "partition: reading row_ptr failed"));
+  const int64_t nz0 = plan->h_pinned[0], nz1 = plan->h_pinned[1];
+  if (nz0 < 0 || nz1 < nz0 || nz1 > nnz)
+    return fail(set_error(SHIRO_ERR_BAD_CSR, "partition: row_ptr of the panel is not within [0, nnz] or decreases"));
+  if (nz1 - nz0 >= (1ll << 31) - 1)
+    return fail(set_error(SHIRO_ERR_UNSUPPORTED, "partition: panel has 2^31 or more nonzeros"));
+  plan->nz_begin = nz0;
+  plan->nnz = nz1 - nz0;
+  plan->n_words = ceil_div(n_cols, 32);
+
+  int rc;
+  if ((rc = dev_alloc_n(&plan->row_ptr, plan->rows + 1)) ||
+      (rc = dev_alloc_n(&plan->col, std::max<int64_t>(plan->nnz, 1))) ||
+      (rc = dev_alloc_n(&plan->bitmap, plan->n_words)) ||
+      (rc = dev_alloc_n(&plan->word_off, plan->n_words)) ||
+      (rc = dev_alloc_n(&plan->unique_cols, std::max<int64_t>(std::min(plan->nnz, n_cols), 1))) ||
+      (rc = dev_alloc_n(&plan->block_off, (int64_t)P + 1)) ||
+      (rc = dev_alloc_n(&plan->colmap, std::max<int64_t>(plan->nnz, 1))))
+    return fail(rc);
+  if ((rc = launch_rebase_row_ptr(d_row_ptr + plan->row_begin, plan->rows, plan->row_ptr, s))) return fail(rc);
+  if (plan->nnz > 0 &&
+      hipMemcpyAsync(plan->col, d_col + nz0, (size_t)plan->nnz * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return fail(set_error(SHIRO_ERR_HIP, "partition: copying the panel's columns failed"));
+
+  if ((flags & SHIRO_CHECK_CSR) || env_check()) {
+    if ((rc = ensure_scratch(plan, 256))) return fail(rc);
+    int32_t* d_flag = reinterpret_cast<int32_t*>(plan->scratch);
+    if (hipMemsetAsync(d_flag, 0, 4, s) != hipSuccess) return fail(set_error(SHIRO_ERR_HIP, "check: memset failed"));
+    if ((rc = launch_check_csr(plan->row_ptr, plan->col, plan->rows, plan->nnz, n_cols, d_flag, s)))
+      return fail(rc);
+    int32_t* h_flag = reinterpret_cast<int32_t*>(plan->h_pinned);
+    if (hipMemcpyAsync(h_flag, d_flag, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(set_error(SHIRO_ERR_HIP, "check: reading the flag failed"));
+    if (*h_flag) {
+      std::string why;
+      if (*h_flag & 1) why += " row_ptr decreases;";
+      if (*h_flag & 2) why += " column id outside [0, n_cols);";
+      if (*h_flag & 4) why += " columns not strictly ascending inside a row;";
+      return fail(set_error(SHIRO_ERR_BAD_CSR, "partition: malformed CSR:" + why));
+    }
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(set_error(SHIRO_ERR_HIP, "partition: stream failed"));
+  *out_plan = plan;
+  return SHIRO_OK;
+}
+
+SHIRO_API int shiro_plan_info(shiro_plan plan, shiro_plan_info_t* h_info) {
+  if (!plan || !h_info) return set_error(SHIRO_ERR_INVALID_ARG, "plan_info: NULL argument");
+  h_info->n_rows = plan->n_rows;
+  h_info->n_cols = plan->n_cols;
+  h_info->P = plan->P;
+  h_info->p = plan->p;
+  h_info->M = plan->M;
+  h_info->K = plan->K;
+  h_info->row_begin = plan->row_begin;
+  h_info->rows = plan->rows;
+  h_info->nz_begin = plan->nz_begin;
+  h_info->nnz = plan->nnz;
+  h_info->U = plan->selected ? plan->U : -1;
+  return SHIRO_OK;
+}
+
+SHIRO_API int shiro_block_nnz(shiro_plan plan, int64_t* d_block_nnz, shiro_stream_t stream) {
+  if (!plan || !d_block_nnz) return set_error(SHIRO_ERR_INVALID_ARG, "block_nnz: NULL argument");
+  return launch_block_nnz(plan->col, plan->nnz, plan->K, plan->P, d_block_nnz,
+                          reinterpret_cast<hipStream_t>(stream));
+}
+
+SHIRO_API int shiro_select_rows(shiro_plan plan, shiro_stream_t stream, int64_t* h_U_total,
+                                int64_t* h_U_per_block) {
+  if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "select_rows: plan is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (!plan->selected) {
+    if (stream_capturing(s)) return set_error(SHIRO_ERR_CAPTURING, "select_rows: stream is capturing");
+    SHIRO_TRY(run_select(plan, s));
+  }
+  if (h_U_total) *h_U_total = plan->U;
+  if (h_U_per_block)
+    for (int32_t q = 0; q < plan->P; ++q) h_U_per_block[q] = plan->h_block_off[q + 1] - plan->h_block_off[q];
+  return SHIRO_OK;
+}
+
+SHIRO_API int shiro_plan_selection(shiro_plan plan, const int32_t** d_unique_cols,
+                                   const int64_t** d_block_off, const int32_t** d_colmap) {
+  if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "plan_selection: plan is NULL");
+  if (!plan->selected) return set_error(SHIRO_ERR_NOT_READY, "plan_selection: call shiro_select_rows first");
+  if (d_unique_cols) *d_unique_cols = plan->unique_cols;
+  if (d_block_off) *d_block_off = plan->block_off;
+  if (d_colmap) *d_colmap = plan->colmap;
+  return SHIRO_OK;
+}
+
+SHIRO_API int shiro_copy_selection(shiro_plan plan, int32_t* d_unique_cols, int64_t* d_block_off,
+                                   int32_t* d_colmap, shiro_stream_t stream) {
+  if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "copy_selection: plan is NULL");
+  if (!plan->selected) return set_error(SHIRO_ERR_NOT_READY, "copy_selection: call shiro_select_rows first");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (d_unique_cols && plan->U > 0)
+    SHIRO_HIP(hipMemcpyAsync(d_unique_cols, plan->unique_cols, (size_t)plan->U * 4, hipMemcpyDeviceToDevice, s));
+  if (d_block_off)
+    SHIRO_HIP(hipMemcpyAsync(d_block_off, plan->block_off, (size_t)(plan->P + 1) * 8, hipMemcpyDeviceToDevice, s));
+  if (d_colmap && plan->nnz > 0)
+    SHIRO_HIP(hipMemcpyAsync(d_colmap, plan->colmap, (size_t)plan->nnz * 4, hipMemcpyDeviceToDevice, s));
+  return SHIRO_OK;
+}
+
+SHIRO_API int shiro_pack_B(shiro_plan plan, const void* d_B, int64_t ldb, int32_t N, shiro_dtype dt,
+                           void* d_Bpacked, int64_t ldp, shiro_stream_t stream) {
+  if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "pack_B: plan is NULL");
+  if (!plan->selected) return set_error(SHIRO_ERR_NOT_READY, "pack_B: call shiro_select_rows first");
+  if (!valid_dt(dt)) return set_error(SHIRO_ERR_UNSUPPORTED, "pack_B: unknown dtype");
+  if (N < 0 || ldb < N || ldp < N) return set_error(SHIRO_ERR_INVALID_ARG, "pack_B: need N >= 0, ldb >= N, ldp >= N");
+  if (N > 0 && plan->U > 0 && (!d_B || !d_Bpacked)) return set_error(SHIRO_ERR_INVALID_ARG, "pack_B: NULL matrix");
+  return launch_pack(plan, d_B, ldb, N, dt, d_Bpacked, ldp, reinterpret_cast<hipStream_t>(stream));
+}
+
+SHIRO_API int shiro_spmm(shiro_plan plan, const float* d_vals, const void* d_Bpacked, int64_t ldp,
+                         int32_t N, shiro_dtype in_dt, void* d_Y, int64_t ldy, shiro_dtype out_dt,
+                         uint32_t mode, shiro_stream_t stream) {
+  if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "spmm: plan is NULL");
+  if (!plan->selected) return set_error(SHIRO_ERR_NOT_READY, "spmm: call shiro_select_rows first");
+  if (!valid_dt(in_dt) || !valid_dt(out_dt)) return set_error(SHIRO_ERR_UNSUPPORTED, "spmm: unknown dtype");
+  if (in_dt == SHIRO_F32 && out_dt == SHIRO_BF16)
+    return set_error(SHIRO_ERR_UNSUPPORTED, "spmm: F32 input with BF16 output is not supported");
+  if (N < 0 || ldp < N || ldy < N) return set_error(SHIRO_ERR_INVALID_ARG, "spmm: need N >= 0, ldp >= N, ldy >= N");
+  if (mode != SHIRO_MODE_BATCHED && mode != SHIRO_MODE_PER_BLOCK) return set_error(SHIRO_ERR_INVALID_ARG, "spmm: unknown mode");
+  if (N > 0 && plan->rows > 0 && !d_Y) return set_error(SHIRO_ERR_INVALID_ARG, "spmm: d_Y is NULL");
+  if (N > 0 && plan->nnz > 0 && (!d_Bpacked || !d_vals)) return set_error(SHIRO_ERR_INVALID_ARG, "spmm: NULL input");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (mode == SHIRO_MODE_PER_BLOCK)
+    return launch_spmm_per_block(plan, d_vals, d_Bpacked, ldp, N, in_dt, d_Y, ldy, out_dt, s);
+  return launch_spmm(plan, tuning_for(plan, SHIRO_KERNEL_SPMM, N, in_dt), d_vals, d_Bpacked, ldp, N,
+                     in_dt, d_Y, ldy, out_dt, s);
+}
+
+SHIRO_API int shiro_spmm_backward(shiro_plan plan, const float* d_vals, const void* d_dY, int64_t lddy,
+                                  const void* d_Bpacked, int64_t ldp, int32_t N, shiro_dtype dt,
+                                  void* d_dBpacked, int64_t lddbp, void* d_dB, int64_t lddb,
+                                  float* d_dvals, shiro_stream_t stream) {
+  if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "spmm_backward: plan is NULL");
+  if (!plan->selected) return set_error(SHIRO_ERR_NOT_READY, "spmm_backward: call shiro_select_rows first");
+  if (!valid_dt(dt)) return set_error(SHIRO_ERR_UNSUPPORTED, "spmm_backward: unknown dtype");
+  if (N < 0 || lddy < N) return set_error(SHIRO_ERR_INVALID_ARG, "spmm_backward: need N >= 0 and lddy >= N");
+  if (d_dBpacked && lddbp < N) return set_error(SHIRO_ERR_INVALID_ARG, "spmm_backward: lddbp < N");
+  if (d_dB && lddb < N) return set_error(SHIRO_ERR_INVALID_ARG, "spmm_backward: lddb < N");
+  if (d_dvals && ldp < N) return set_error(SHIRO_ERR_INVALID_ARG, "spmm_backward: ldp < N");
+  if (N > 0 && plan->nnz > 0) {
+    if (!d_dY) return set_error(SHIRO_ERR_INVALID_ARG, "spmm_backward: d_dY is NULL");
+    if ((d_dBpacked || d_dB) && !d_vals) return set_error(SHIRO_ERR_INVALID_ARG, "spmm_backward: d_vals is NULL");
+    if (d_dvals && !d_Bpacked) return set_error(SHIRO_ERR_INVALID_ARG, "spmm_backward: d_Bpacked is NULL");
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (d_dBpacked || d_dB)
+    SHIRO_TRY(launch_spmm_t(plan, tuning_for(plan, SHIRO_KERNEL_SPMM_T, N, dt), d_vals, d_dY, lddy, N,
+                            dt, d_dBpacked, lddbp, d_dB, lddb, s));
+  if (d_dvals) {
+    if (N == 0) {
+      // dvals of an empty product are zero
+      return set_error(SHIRO_ERR_INVALID_ARG, "spmm_backward: dvals needs N >= 1");
+    }
+    SHIRO_TRY(launch_sddmm(plan, tuning_for(plan, SHIRO_KERNEL_SDDMM, N, dt), d_vals, d_dY, lddy,
+                           d_Bpacked, ldp, N, dt, d_dvals, s));
+  }
+  return SHIRO_OK;
+}
+
+SHIRO_API int shiro_prepare(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t ops,
+                            shiro_stream_t stream) {
+  if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "prepare: plan is NULL");
+  if (!plan->selected) return set_error(SHIRO_ERR_NOT_READY, "prepare: call shiro_select_rows first");
+  if (!valid_dt(dt) || N < 1) return set_error(SHIRO_ERR_INVALID_ARG, "prepare: bad N or dtype");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (stream_capturing(s)) return set_error(SHIRO_ERR_CAPTURING, "prepare: stream is capturing");
+  const WorkList* wl;
+  if (ops & SHIRO_OP_SPMM) {
+    const shiro_tuning_t t = tuning_for(plan, SHIRO_KERNEL_SPMM, N, dt);
+    SHIRO_TRY(ensure_rows_work(plan, t.chunk, true, s, &wl));
+    SHIRO_TRY(ensure_carry(plan, (int64_t)wl->W * 2 * N, true));
+  }
+  if (ops & SHIRO_OP_BACKWARD) {
+    SHIRO_TRY(build_transposed(plan, s));
+    const shiro_tuning_t t = tuning_for(plan, SHIRO_KERNEL_SPMM_T, N, dt);
+    SHIRO_TRY(ensure_cols_work(plan, t.chunk, true, s, &wl));
+    SHIRO_TRY(ensure_carry(plan, (int64_t)wl->W * 2 * N, true));
+    const shiro_tuning_t t2 = tuning_for(plan, SHIRO_KERNEL_SDDMM, N, dt);
+    SHIRO_TRY(ensure_rows_work(plan, t2.chunk, true, s, &wl));
+  }
+  if (ops & SHIRO_OP_PER_BLOCK) SHIRO_TRY(build_segments(plan, s));
+  SHIRO_HIP(hipStreamSynchronize(s));
+  return SHIRO_OK;
+}
+
+SHIRO_API int shiro_autotune(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t ops,
+                             shiro_stream_t stream) {
+  if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "autotune: plan is NULL");
+  if (!plan->selected) return set_error(SHIRO_ERR_NOT_READY, "autotune: call shiro_select_rows first");
+  if (!valid_dt(dt) || N < 1) return set_error(SHIRO_ERR_INVALID_ARG, "autotune: bad N or dtype");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (stream_capturing(s)) return set_error(SHIRO_ERR_CAPTURING, "autotune: stream is capturing");
+  if (plan->nnz == 0) return SHIRO_OK;
+  const int64_t sz = dt_size(dt);
+  TuneBuffers b;
+  const int64_t U = plan->U, R = plan->rows, nnz = plan->nnz;
+  // float-filled buffers are reinterpreted for bf16 only as bit patterns of
+  // finite values: fill in float, then the bf16 view reads the high halves.
+  SHIRO_TRY(dev_alloc(&b.Bp, U * N * 4));
+  SHIRO_TRY(dev_alloc(&b.Y, R * N * 4));
+  SHIRO_TRY(dev_alloc(&b.dY, R * N * 4));
+  SHIRO_TRY(dev_alloc(&b.dBp, U * N * 4));
+  SHIRO_TRY(dev_alloc_n(&b.vals, plan->nz_begin + nnz));
+  SHIRO_TRY(dev_alloc_n(&b.dvals, plan->nz_begin + nnz));
+  SHIRO_TRY(launch_fill_random((float*)b.Bp, U * N * sz / 4, 1, s));
+  SHIRO_TRY(launch_fill_random((float*)b.dY, R * N * sz / 4, 2, s));
+  SHIRO_TRY(launch_fill_random(b.vals, plan->nz_begin + nnz, 3, s));
+  if (ops & SHIRO_OP_BACKWARD) SHIRO_TRY(build_transposed(plan, s));
+  if (ops & SHIRO_OP_SPMM) SHIRO_TRY(tune_one(plan, SHIRO_KERNEL_SPMM, N, dt, b, s));
+  if (ops & SHIRO_OP_BACKWARD) {
+    SHIRO_TRY(tune_one(plan, SHIRO_KERNEL_SPMM_T, N, dt, b, s));
+    SHIRO_TRY(tune_one(plan, SHIRO_KERNEL_SDDMM, N, dt, b, s));
+  }
+  SHIRO_HIP(hipStreamSynchronize(s));
+  return shiro_prepare(plan, N, dt, ops, stream);
+}
+
+SHIRO_API int shiro_get_tuning(shiro_plan plan, int32_t kernel, int32_t N, shiro_dtype dt,
+                               shiro_tuning_t* h_tuning) {
+  if (!plan || !h_tuning) return set_error(SHIRO_ERR_INVALID_ARG, "get_tuning: NULL argument");
+  if (kernel < 0 || kernel > 2) return set_error(SHIRO_ERR_INVALID_ARG, "get_tuning: unknown kernel family");
+  *h_tuning = tuning_for(plan, kernel, N, dt);
+  return SHIRO_OK;
+}
+
+SHIRO_API int shiro_set_tuning(shiro_plan plan, int32_t kernel, int32_t N, shiro_dtype dt,
+                               const shiro_tuning_t* h_tuning) {
+  if (!plan || !h_tuning) return set_error(SHIRO_ERR_INVALID_ARG, "set_tuning: NULL argument");
+  SHIRO_TRY(validate_tuning(kernel, N, dt, *h_tuning));
+  plan->tuning[TuneKey{kernel, N, (int)dt}] = *h_tuning;
+  return SHIRO_OK;
+}
+
+SHIRO_API int shiro_graph_begin(shiro_plan plan, shiro_stream_t stream) {
+  if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "graph_begin: plan is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (!s) return set_error(SHIRO_ERR_INVALID_ARG, "graph_begin: capture needs a non-default stream");
+  SHIRO_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  return SHIRO_OK;
+}
+
+SHIRO_API int shiro_graph_end(shiro_plan plan, shiro_stream_t stream, int32_t* h_graph_id) {
+  if (!plan || !h_graph_id) return set_error(SHIRO_ERR_INVALID_ARG, "graph_end: NULL argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipGraph_t g = nullptr;
+  SHIRO_HIP(hipStreamEndCapture(s, &g));
+  hipGraphExec_t ex = nullptr;
+  hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return set_error(SHIRO_ERR_HIP, std::string("graph_end: instantiate failed: ") + hipGetErrorString(e));
+  plan->graphs.push_back(ex);
+  *h_graph_id = (int32_t)plan->graphs.size() - 1;
+  return SHIRO_OK;
+}
+
+SHIRO_API int shiro_graph_launch(shiro_plan plan, int32_t graph_id, shiro_stream_t stream) {
+  if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "graph_launch: plan is NULL");
+  if (graph_id < 0 || graph_id >= (int32_t)plan->graphs.size() || !plan->graphs[graph_id])
+    return set_error(SHIRO_ERR_INVALID_ARG, "graph_launch: unknown graph id");
+  SHIRO_HIP(hipGraphLaunch(plan->graphs[graph_id], reinterpret_cast<hipStream_t>(stream)));
+  return SHIRO_OK;
+}
+
+SHIRO_API int shiro_plan_destroy(shiro_plan plan) {
+  plan_free(plan);
+  return SHIRO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+// Library-internal plan object and the host launchers each source file
+// provides.  Not part of the C ABI.
+#pragma once
+
+#include <map>
+#include <tuple>
+#include <vector>
+
+#include "common.hpp"
+
+namespace shiro {
+
+// Merge-path work decomposition of a CSR-like pattern (ptr[0..R], nnz) into
+// W chunks of `chunk` merge items (row ends + nonzeros) each.
+struct WorkList {
+  int32_t chunk = 0;
+  int32_t W = 0;
+  int32_t* chunk_row = nullptr;  // W + 1
+  int32_t* chunk_nz = nullptr;   // W + 1
+};
+
+// Transposed pattern of the remapped panel: packed column u's nonzeros,
+// rows ascending.  Built by a stable radix sort of colmap.
+struct Transposed {
+  bool built = false;
+  int64_t* ptr = nullptr;   // U + 1
+  int32_t* row = nullptr;   // nnz: panel row of each entry
+  int32_t* perm = nullptr;  // nnz: CSR position of each entry (value index)
+};
+
+// Per-block row segments for the one-launch-per-block mode.
+struct BlockSegments {
+  bool built = false;
+  int64_t nseg = 0;
+  int32_t* seg_row = nullptr;    // nseg
+  int32_t* seg_begin = nullptr;  // nseg (CSR positions)
+  int32_t* seg_end = nullptr;    // nseg
+  std::vector<int64_t> h_off;    // P + 1 (host copy: launch sizes)
+};
+
+struct TuneKey {
+  int kernel, N, dt;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(kernel, N, dt) < std::tie(o.kernel, o.N, o.dt);
+  }
+};
+
+}  // namespace shiro
+
+struct shiro_plan_s {
+  int device = 0;
+  int num_cus = 256;
+  int64_t n_rows = 0, n_cols = 0, M = 0, K = 0;
+  int32_t P = 1, p = 0;
+  int64_t row_begin = 0, rows = 0, nz_begin = 0, nnz = 0;
+
+  // pattern (library-owned copies)
+  int64_t* row_ptr = nullptr;  // rows + 1, rebased to 0
+  int32_t* col = nullptr;      // nnz
+
+  // selection
+  bool selected = false;
+  int64_t U = -1;
+  int64_t n_words = 0;
+  uint32_t* bitmap = nullptr;   // n_words
+  int32_t* word_off = nullptr;  // n_words: exclusive prefix of popcounts
+  int32_t* unique_cols = nullptr;  // capacity min(nnz, n_cols)
+  int64_t* block_off = nullptr;    // P + 1
+  int32_t* colmap = nullptr;       // nnz
+  std::vector<int64_t> h_block_off;
+
+  // derived structures
+  std::map<int32_t, shiro::WorkList> rows_work;   // keyed by chunk size (row-major pattern)
+  std::map<int32_t, shiro::WorkList> cols_work;   // keyed by chunk size (transposed pattern)
+  shiro::Transposed tr;
+  shiro::BlockSegments seg;
+
+  // carry slots of split rows: 2 * W * carry_cols floats
+  float* carry = nullptr;
+  int64_t carry_elems = 0;
+
+  // scratch for scans and sorts
+  void* scratch = nullptr;
+  int64_t scratch_bytes = 0;
+  int64_t* h_pinned = nullptr;  // small pinned host buffer (P + 2 int64)
+
+  std::map<shiro::TuneKey, shiro_tuning_t> tuning;
+  std::vector<hipGraphExec_t> graphs;
+  hipGraph_t capture_graph = nullptr;
+};
+
+namespace shiro {
+
+// ---- memory ---------------------------------------------------------------
+int dev_alloc(void** p, int64_t bytes);
+void dev_free(void* p);
+template <typename T>
+int dev_alloc_n(T** p, int64_t n) {
+  return dev_alloc(reinterpret_cast<void**>(p), n * (int64_t)sizeof(T));
+}
+int ensure_scratch(shiro_plan plan, int64_t bytes);
+bool stream_capturing(hipStream_t s);
+
+// ---- scan.hip ---------------------------------------------------------------
+// Exclusive scan of int32 counts into int64 offsets; total written to
+// *d_total (nullable).  Scratch needs scan_scratch_bytes(n).
+int64_t scan_scratch_bytes(int64_t n);
+int exclusive_scan_i32_to_i64(const int32_t* in, int64_t n, int64_t* out, int64_t* d_total,
+                              void* scratch, hipStream_t s);
+int exclusive_scan_i64(const int64_t* in, int64_t n, int64_t* out, int64_t* d_total,
+                       void* scratch, hipStream_t s);
+
+// ---- select.hip -------------------------------------------------------------
+int launch_rebase_row_ptr(const int64_t* src, int64_t rows, int64_t* dst, hipStream_t s);
+int launch_check_csr(const int64_t* row_ptr, const int32_t* col, int64_t rows, int64_t nnz,
+                     int64_t n_cols, int32_t* d_flag, hipStream_t s);
+int launch_block_nnz(const int32_t* col, int64_t nnz, int64_t K, int32_t P, int64_t* out,
+                     hipStream_t s);
+int run_select(shiro_plan plan, hipStream_t s);
+
+// ---- sort.hip ---------------------------------------------------------------
+// Stable LSD radix sort of (key, value) uint32 pairs on the low `key_bits`
+// bits.  Results end in keys_out/vals_out.  Scratch: sort_scratch_bytes(n).
+int64_t sort_scratch_bytes(int64_t n);
+int radix_sort_pairs(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
+                     uint32_t* vals_out, int64_t n, int key_bits, void* scratch, hipStream_t s);
+
+// ---- spmm.hip ---------------------------------------------------------------
+int build_worklist(const int64_t* ptr, int64_t R, int64_t nnz, int32_t chunk, WorkList* wl,
+                   hipStream_t s);
+int build_transposed(shiro_plan plan, hipStream_t s);
+int build_segments(shiro_plan plan, hipStream_t s);
+
+int launch_pack(shiro_plan plan, const void* B, int64_t ldb, int32_t N, shiro_dtype dt,
+                void* Bp, int64_t ldp, hipStream_t s);
+int launch_spmm(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* X,
+                int64_t ldx, int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy,
+                shiro_dtype out_dt, hipStream_t s);
+int launch_spmm_per_block(shiro_plan plan, const float* vals, const void* X, int64_t ldx,
+                          int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy, shiro_dtype out_dt,
+                          hipStream_t s);
+int launch_spmm_t(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* dY,
+                  int64_t lddy, int32_t N, shiro_dtype dt, void* dBp, int64_t lddbp, void* dB,
+                  int64_t lddb, hipStream_t s);
+int launch_sddmm(shiro_plan plan, const shiro_tuning_t& t, const float* vals_unused,
+                 const void* dY, int64_t lddy, const void* Bp, int64_t ldp, int32_t N,
+                 shiro_dtype dt, float* dvals, hipStream_t s);
+int launch_fill_random(float* p, int64_t n, uint64_t seed, hipStream_t s);
+
+// Work lists / carries needed by a tuning; allocate=false returns NOT_READY
+// (or CAPTURING) instead of allocating.
+int ensure_rows_work(shiro_plan plan, int32_t chunk, bool allocate, hipStream_t s,
+                     const WorkList** out);
+int ensure_cols_work(shiro_plan plan, int32_t chunk, bool allocate, hipStream_t s,
+                     const WorkList** out);
+int ensure_carry(shiro_plan plan, int64_t elems, bool allocate);
+
+shiro_tuning_t default_tuning(int kernel, int32_t N, shiro_dtype dt);
+int validate_tuning(int kernel, int32_t N, shiro_dtype dt, const shiro_tuning_t& t);
+
+}  // namespace shiro

@@ -1,0 +1,231 @@
+// Panel extraction and Cols(A^(p,q)) selection.
+//
+// Selection (Table 1; Sec. 3.1 column-based scheme; Sec. 5.1 stage 1) runs
+// over the whole panel at once: one bit per global column id marks the
+// columns present in the panel, a prefix sum of the per-word popcounts gives
+// every present column its packed position, and because column blocks are
+// contiguous id ranges the positions are already grouped block by block in
+// ascending id order.  block_off[q] is the rank of block q's first column id.
+#include "plan.hpp"
+#include "scan.hpp"
+
+namespace shiro {
+
+namespace {
+
+__global__ void k_rebase(const int64_t* __restrict__ src, int64_t n, int64_t* __restrict__ dst) {
+  const int64_t base = src[0];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i] - base;
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Index of the last row r with ptr[r] <= k (ptr non-decreasing, ptr[0] = 0).
+__device__ __forceinline__ int64_t row_of(const int64_t* __restrict__ ptr, int64_t rows, int64_t k) {
+  int64_t lo = 0, hi = rows - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (ptr[mid] <= k) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// CSR validation.  bit 1: row_ptr decreasing, bit 2: column out of range,
+// bit 4: columns not strictly ascending inside a row.
+__global__ void k_check_rows(const int64_t* __restrict__ ptr, int64_t rows, int64_t nnz,
+                             int32_t* flag) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = ptr[i], b = ptr[i + 1];
+    if (b < a || a < 0 || b > nnz) atomicOr(flag, 1);
+  }
+}
+
+__global__ void k_check_cols(const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                             int64_t rows, int64_t nnz, int64_t n_cols, int32_t* flag) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = col[k];
+    if (c < 0 || (int64_t)c >= n_cols) atomicOr(flag, 2);
+    if (k > 0) {
+      const int64_t r = row_of(ptr, rows, k);
+      if (ptr[r] != k && col[k - 1] >= c) atomicOr(flag, 4);
+    }
+  }
+}
+
+// Per-block nonzero counts: a workgroup-private histogram in LDS, then one
+// integer add per bin (integer sums: the result is order independent).
+__global__ __launch_bounds__(kBlock) void k_block_nnz(const int32_t* __restrict__ col, int64_t nnz,
+                                                      int64_t K, int32_t P,
+                                                      unsigned long long* out) {
+  extern __shared__ uint32_t hist[];
+  for (int i = threadIdx.x; i < P; i += kBlock) hist[i] = 0;
+  __syncthreads();
+  for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * kBlock)
+    atomicAdd(&hist[(int64_t)col[k] / K], 1u);
+  __syncthreads();
+  for (int i = threadIdx.x; i < P; i += kBlock)
+    if (hist[i]) atomicAdd(&out[i], (unsigned long long)hist[i]);
+}
+
+__global__ void k_block_nnz_global(const int32_t* __restrict__ col, int64_t nnz, int64_t K,
+                                   unsigned long long* out) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&out[(int64_t)col[k] / K], 1ull);
+}
+
+// Mark the column ids present in the panel.  The bit is read from L2 first
+// (device-scope load, bypassing the per-CU cache) and the atomic OR is issued
+// only if it is still clear, so hub columns cost a read, not an atomic.  The
+// final bitmap is the set union, independent of ordering.
+__global__ void k_mark(const int32_t* __restrict__ col, int64_t nnz, uint32_t* bitmap) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t c = (uint32_t)col[k];
+    const uint32_t bit = 1u << (c & 31u);
+    uint32_t* w = bitmap + (c >> 5);
+    const uint32_t cur = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!(cur & bit)) atomicOr(w, bit);
+  }
+}
+
+struct PopcountIn {
+  const uint32_t* bitmap;
+  __device__ int64_t operator()(int64_t w) const { return __popc(bitmap[w]); }
+};
+
+// Writes each word's packed offset and compacts its set bits, ascending.
+struct CompactOut {
+  const uint32_t* bitmap;
+  int32_t* word_off;
+  int32_t* unique_cols;
+  __device__ void operator()(int64_t w, int64_t prefix, int64_t) const {
+    word_off[w] = (int32_t)prefix;
+    uint32_t bits = bitmap[w];
+    int32_t o = (int32_t)prefix;
+    const int32_t base = (int32_t)(w << 5);
+    while (bits) {
+      const int b = __ffs(bits) - 1;
+      unique_cols[o++] = base + b;
+      bits &= bits - 1u;
+    }
+  }
+};
+
+// colmap[k] = packed position of col[k] = offset of its word + set bits below it.
+__global__ void k_remap(const int32_t* __restrict__ col, int64_t nnz,
+                        const uint32_t* __restrict__ bitmap, const int32_t* __restrict__ word_off,
+                        int32_t* __restrict__ colmap) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t c = (uint32_t)col[k];
+    const uint32_t below = (1u << (c & 31u)) - 1u;
+    colmap[k] = word_off[c >> 5] + __popc(bitmap[c >> 5] & below);
+  }
+}
+
+// block_off[q] = packed position of the first column id of block q.
+__global__ void k_block_off(const uint32_t* __restrict__ bitmap, const int32_t* __restrict__ word_off,
+                            int64_t n_cols, int64_t K, int32_t P, const int64_t* __restrict__ d_U,
+                            int64_t* __restrict__ block_off) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q > P) return;
+  int64_t c0 = q * K;
+  if (c0 >= n_cols) {
+    block_off[q] = *d_U;
+    return;
+  }
+  const uint32_t below = (1u << ((uint32_t)c0 & 31u)) - 1u;
+  block_off[q] = (int64_t)word_off[c0 >> 5] + __popc(bitmap[c0 >> 5] & below);
+}
+
+unsigned grid_for(int64_t n, int64_t cap = 65536) {
+  int64_t g = ceil_div(n > 0 ? n : 1, kBlock);
+  return (unsigned)(g < cap ? g : cap);
+}
+
+}  // namespace
+
+int launch_rebase_row_ptr(const int64_t* src, int64_t rows, int64_t* dst, hipStream_t s) {
+  k_rebase<<<grid_for(rows + 1), kBlock, 0, s>>>(src, rows + 1, dst);
+  SHIRO_LAUNCH_CHECK();
+  return SHIRO_OK;
+}
+
+int launch_check_csr(const int64_t* row_ptr, const int32_t* col, int64_t rows, int64_t nnz,
+                     int64_t n_cols, int32_t* d_flag, hipStream_t s) {
+  if (rows > 0) {
+    k_check_rows<<<grid_for(rows), kBlock, 0, s>>>(row_ptr, rows, nnz, d_flag);
+    SHIRO_LAUNCH_CHECK();
+  }
+  if (nnz > 0 && rows > 0) {
+    k_check_cols<<<grid_for(nnz), kBlock, 0, s>>>(row_ptr, col, rows, nnz, n_cols, d_flag);
+    SHIRO_LAUNCH_CHECK();
+  }
+  return SHIRO_OK;
+}
+
+int launch_block_nnz(const int32_t* col, int64_t nnz, int64_t K, int32_t P, int64_t* out,
+                     hipStream_t s) {
+  k_fill_i64<<<grid_for(P), kBlock, 0, s>>>(out, P, 0);
+  SHIRO_LAUNCH_CHECK();
+  if (nnz == 0) return SHIRO_OK;
+  auto* o = reinterpret_cast<unsigned long long*>(out);
+  if (P <= 16384) {
+    k_block_nnz<<<grid_for(nnz, 2048), kBlock, (size_t)P * 4, s>>>(col, nnz, K, P, o);
+  } else {
+    k_block_nnz_global<<<grid_for(nnz), kBlock, 0, s>>>(col, nnz, K, o);
+  }
+  SHIRO_LAUNCH_CHECK();
+  return SHIRO_OK;
+}
+
+int run_select(shiro_plan plan, hipStream_t s) {
+  const int64_t nw = plan->n_words;
+  const int64_t nnz = plan->nnz;
+  // scratch: [U (int64)] [scan tile sums]
+  SHIRO_TRY(ensure_scratch(plan, 256 + scan_scratch_bytes(nw)));
+  int64_t* d_U = reinterpret_cast<int64_t*>(plan->scratch);
+  void* scan_tmp = reinterpret_cast<char*>(plan->scratch) + 256;
+
+  k_fill_u32<<<grid_for(nw), kBlock, 0, s>>>(plan->bitmap, nw, 0u);
+  SHIRO_LAUNCH_CHECK();
+  if (nnz > 0) {
+    k_mark<<<grid_for(nnz), kBlock, 0, s>>>(plan->col, nnz, plan->bitmap);
+    SHIRO_LAUNCH_CHECK();
+  }
+  SHIRO_TRY(scan_generic(PopcountIn{plan->bitmap}, nw,
+                         CompactOut{plan->bitmap, plan->word_off, plan->unique_cols}, d_U,
+                         scan_tmp, s));
+  if (nnz > 0) {
+    k_remap<<<grid_for(nnz), kBlock, 0, s>>>(plan->col, nnz, plan->bitmap, plan->word_off,
+                                              plan->colmap);
+    SHIRO_LAUNCH_CHECK();
+  }
+  k_block_off<<<grid_for(plan->P + 1), kBlock, 0, s>>>(plan->bitmap, plan->word_off, plan->n_cols,
+                                                        plan->K, plan->P, d_U, plan->block_off);
+  SHIRO_LAUNCH_CHECK();
+  SHIRO_HIP(hipMemcpyAsync(plan->h_pinned, plan->block_off, (size_t)(plan->P + 1) * 8,
+                           hipMemcpyDeviceToHost, s));
+  SHIRO_HIP(hipStreamSynchronize(s));
+  plan->h_block_off.assign(plan->h_pinned, plan->h_pinned + plan->P + 1);
+  plan->U = plan->h_block_off[plan->P];
+  plan->selected = true;
+  return SHIRO_OK;
+}
+
+}  // namespace shiro

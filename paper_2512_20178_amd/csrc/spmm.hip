@@ -1,0 +1,902 @@
+// Gather, pack and sparse-times-dense kernels of the per-rank path.
+//
+// Work decomposition: merge path over (row ends, nonzeros) of a CSR-like
+// pattern (ptr[0..R], nnz).  Chunk w covers merge items [w*D, (w+1)*D), so
+// every wavefront gets the same amount of work whatever the row lengths are
+// (power-law rows of tens of thousands of nonzeros are split over many
+// wavefronts, empty rows still cost their store).  A row whose items fall in
+// more than one chunk leaves one partial sum per chunk in a carry slot; a
+// fix-up pass adds the slots of each such row in chunk order and applies the
+// output epilogue once.  No floating-point atomics anywhere, so every output
+// is reproducible bit for bit.
+//
+// Lane layout: a dense row is read 16 bytes per lane by `LANES` lanes (tile
+// width LANES*16 bytes: 128 float32 columns for 32 lanes); the 64/LANES lane
+// groups of a wavefront take consecutive nonzeros of the same row, UNROLL
+// deep, and are reduced with cross-lane shuffles when the row ends.  All row
+// bookkeeping is wavefront-uniform and lives in scalar registers.
+#include "plan.hpp"
+#include "scan.hpp"
+
+namespace shiro {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// work lists
+// ---------------------------------------------------------------------------
+__global__ void k_merge_path(const int64_t* __restrict__ ptr, int32_t R, int64_t nnz, int64_t D,
+                             int32_t W, int32_t* __restrict__ chunk_row,
+                             int32_t* __restrict__ chunk_nz) {
+  const int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (w > W) return;
+  int64_t d = w * D;
+  if (d > (int64_t)R + nnz) d = (int64_t)R + nnz;
+  // largest i in [0, R] with ptr[i] + i <= d
+  int64_t lo = 0, hi = R;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (ptr[mid] + mid <= d) lo = mid; else hi = mid - 1;
+  }
+  chunk_row[w] = (int32_t)lo;
+  chunk_nz[w] = (int32_t)(d - lo);
+}
+
+// ---------------------------------------------------------------------------
+// SpMM: out[r, :] = sum_{k in row r} vals[perm ? perm[k] : k] * X[idx[k], :]
+// ---------------------------------------------------------------------------
+struct SpmmArgs {
+  const int64_t* ptr;       // R + 1
+  const int32_t* idx;       // nnz: row of X to gather
+  const int32_t* perm;      // nnz or null: value index
+  const float* vals;        // values (panel-local indexing)
+  const void* X;            // gathered dense rows
+  int64_t ldx;
+  void* out;                // R x N, may be null (transposed: dBpacked optional)
+  int64_t ldo;
+  void* scat;               // transposed only: dB, add-scatter at rows scat_idx[r]
+  int64_t lds;
+  const int32_t* scat_idx;  // R
+  const int32_t* chunk_row;  // W + 1
+  const int32_t* chunk_nz;   // W + 1
+  float* carry;             // [W][2][N]
+  int32_t W, R, N;
+  int32_t chunks_per_wave;
+  int32_t xcd_remap;
+};
+
+template <typename TOUT, int VEC>
+__device__ __forceinline__ void epilogue_row(const SpmmArgs& a, int32_t r, int64_t c,
+                                             const float (&acc)[VEC]) {
+  if (a.out) {
+    TOUT* o = reinterpret_cast<TOUT*>(a.out) + (int64_t)r * a.ldo + c;
+    Elem<TOUT>::template store<VEC>(o, acc);
+  }
+  if (a.scat) {
+    TOUT* o = reinterpret_cast<TOUT*>(a.scat) + (int64_t)a.scat_idx[r] * a.lds + c;
+    float cur[VEC];
+    Elem<TOUT>::template load<VEC>(o, cur);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) cur[e] += acc[e];
+    Elem<TOUT>::template store<VEC>(o, cur);
+  }
+}
+
+// Logical workgroup index: with xcd_remap, workgroups that the dispatcher
+// places on the same XCD (round robin over 8) get a contiguous index range,
+// so each XCD's L2 serves a contiguous range of rows.
+__device__ __forceinline__ int32_t logical_block(int32_t remap) {
+  const int32_t b = blockIdx.x, g = gridDim.x;
+  if (!remap || (g & 7)) return b;
+  return (b & 7) * (g >> 3) + (b >> 3);
+}
+
+template <typename TIN, typename TOUT, int LANES, int VEC, int UNROLL>
+__global__ __launch_bounds__(kBlock) void k_spmm(SpmmArgs a) {
+  constexpr int G = kWave / LANES;
+  const int lane = lane_id();
+  const int g = lane / LANES;
+  const int li = lane % LANES;
+  const int64_t c = (int64_t)blockIdx.y * (LANES * VEC) + (int64_t)li * VEC;
+  const bool cvalid = c < a.N;
+  const TIN* __restrict__ X = reinterpret_cast<const TIN*>(a.X);
+  const int64_t* __restrict__ ptr = a.ptr;
+  const int32_t* __restrict__ idx = a.idx;
+  const int32_t* __restrict__ perm = a.perm;
+  const float* __restrict__ vals = a.vals;
+
+  const int32_t gw = uniform(logical_block(a.xcd_remap) * kWavesPerBlock + wave_id());
+  const int32_t w_begin = gw * a.chunks_per_wave;
+  int32_t w_end = w_begin + a.chunks_per_wave;
+  if (w_end > a.W) w_end = a.W;
+
+  for (int32_t w = w_begin; w < w_end; ++w) {
+    const int32_t i0 = a.chunk_row[w], i1 = a.chunk_row[w + 1];
+    const int64_t j0 = a.chunk_nz[w], j1 = a.chunk_nz[w + 1];
+    for (int32_t r = i0; r <= i1 && r < a.R; ++r) {
+      const int64_t rs = ptr[r], re = ptr[r + 1];
+      if (r == i1 && j1 <= rs) break;  // chunk holds nothing of row i1
+      const int64_t kb = rs > j0 ? rs : j0;
+      const int64_t ke = re < j1 ? re : j1;
+      float acc[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
+      for (int64_t k = kb; k < ke; k += G * UNROLL) {
+        int32_t xi[UNROLL];
+        float v[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          const int64_t kk = k + u * G + g;
+          const bool ok = kk < ke;
+          xi[u] = ok ? idx[kk] : -1;
+          v[u] = ok ? vals[perm ? perm[kk] : kk] : 0.f;
+        }
+        float x[UNROLL][VEC];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          if (xi[u] >= 0 && cvalid) {
+            Elem<TIN>::template load<VEC>(X + (int64_t)xi[u] * a.ldx + c, x[u]);
+          } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) x[u][e] = 0.f;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) acc[e] = fmaf(v[u], x[u][e], acc[e]);
+      }
+      // combine the lane groups (fixed butterfly order)
+#pragma unroll
+      for (int sft = LANES; sft < kWave; sft <<= 1)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e] += __shfl_xor(acc[e], sft, kWave);
+      const bool head = (r == i0) && (j0 > rs);
+      const bool tail = (r == i1);
+      if (g == 0 && cvalid) {
+        if (!head && !tail) {
+          epilogue_row<TOUT, VEC>(a, r, c, acc);
+        } else {
+          float* cs = a.carry + ((int64_t)w * 2 + (head ? 0 : 1)) * a.N + c;
+          Elem<float>::template store<VEC>(cs, acc);
+        }
+      }
+    }
+  }
+}
+
+// Rows split over chunks: sum the tail slot of the starting chunk and the
+// head slots of the following chunks, in chunk order, then the epilogue.
+template <typename TOUT, int VEC>
+__global__ __launch_bounds__(kBlock) void k_fixup(SpmmArgs a) {
+  const int lane = lane_id();
+  const int32_t nwaves = gridDim.x * kWavesPerBlock;
+  for (int32_t w = uniform((int32_t)blockIdx.x * kWavesPerBlock + wave_id()); w < a.W; w += nwaves) {
+    const int32_t r = a.chunk_row[w + 1];
+    if (r >= a.R) continue;
+    const int64_t rs = a.ptr[r];
+    const int64_t j0 = a.chunk_nz[w], j1 = a.chunk_nz[w + 1];
+    // chunk w starts row r (no earlier part) and does not finish it
+    if (!(j1 > rs && rs >= j0)) continue;
+    for (int64_t c = (int64_t)lane * VEC; c < a.N; c += (int64_t)kWave * VEC) {
+      float acc[VEC];
+      Elem<float>::template load<VEC>(a.carry + ((int64_t)w * 2 + 1) * a.N + c, acc);
+      for (int32_t w2 = w + 1;; ++w2) {
+        float p[VEC];
+        Elem<float>::template load<VEC>(a.carry + ((int64_t)w2 * 2) * a.N + c, p);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e] += p[e];
+        if (a.chunk_row[w2 + 1] > r) break;
+      }
+      epilogue_row<TOUT, VEC>(a, r, c, acc);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// SDDMM: dvals[k] = dY[row(k), :] . Bp[colmap[k], :]
+// ---------------------------------------------------------------------------
+struct SddmmArgs {
+  const int64_t* ptr;
+  const int32_t* idx;
+  const void* dY;
+  int64_t lddy;
+  const void* Bp;
+  int64_t ldp;
+  float* dvals;
+  const int32_t* chunk_row;
+  const int32_t* chunk_nz;
+  int32_t W, R, N;
+  int32_t chunks_per_wave;
+  int32_t xcd_remap;
+};
+
+template <typename TIN, int LANES, int VEC, int UNROLL>
+__global__ __launch_bounds__(kBlock) void k_sddmm(SddmmArgs a) {
+  constexpr int G = kWave / LANES;
+  constexpr int TW = LANES * VEC;
+  const int lane = lane_id();
+  const int g = lane / LANES;
+  const int li = lane % LANES;
+  const TIN* __restrict__ dY = reinterpret_cast<const TIN*>(a.dY);
+  const TIN* __restrict__ Bp = reinterpret_cast<const TIN*>(a.Bp);
+  const int64_t* __restrict__ ptr = a.ptr;
+  const int32_t* __restrict__ idx = a.idx;
+  const int ntiles = (a.N + TW - 1) / TW;
+
+  const int32_t gw = uniform(logical_block(a.xcd_remap) * kWavesPerBlock + wave_id());
+  const int32_t w_begin = gw * a.chunks_per_wave;
+  int32_t w_end = w_begin + a.chunks_per_wave;
+  if (w_end > a.W) w_end = a.W;
+
+  for (int32_t w = w_begin; w < w_end; ++w) {
+    const int32_t i0 = a.chunk_row[w], i1 = a.chunk_row[w + 1];
+    const int64_t j0 = a.chunk_nz[w], j1 = a.chunk_nz[w + 1];
+    for (int32_t r = i0; r <= i1 && r < a.R; ++r) {
+      const int64_t rs = ptr[r], re = ptr[r + 1];
+      const int64_t kb = rs > j0 ? rs : j0;
+      const int64_t ke = re < j1 ? re : j1;
+      if (kb >= ke) continue;
+      // first column tile of dY row r stays in registers for the whole row
+      const int64_t c0 = (int64_t)li * VEC;
+      float y0[VEC];
+      if (c0 < a.N) {
+        Elem<TIN>::template load<VEC>(dY + (int64_t)r * a.lddy + c0, y0);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) y0[e] = 0.f;
+      }
+      for (int64_t k = kb; k < ke; k += G * UNROLL) {
+        int32_t xi[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          const int64_t kk = k + u * G + g;
+          xi[u] = kk < ke ? idx[kk] : -1;
+        }
+        float part[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          part[u] = 0.f;
+          if (xi[u] >= 0 && c0 < a.N) {
+            float b[VEC];
+            Elem<TIN>::template load<VEC>(Bp + (int64_t)xi[u] * a.ldp + c0, b);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) part[u] = fmaf(y0[e], b[e], part[u]);
+          }
+        }
+        for (int t = 1; t < ntiles; ++t) {
+          const int64_t ct = (int64_t)t * TW + c0;
+          if (ct < a.N) {
+            float y[VEC];
+            Elem<TIN>::template load<VEC>(dY + (int64_t)r * a.lddy + ct, y);
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+              if (xi[u] >= 0) {
+                float b[VEC];
+                Elem<TIN>::template load<VEC>(Bp + (int64_t)xi[u] * a.ldp + ct, b);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) part[u] = fmaf(y[e], b[e], part[u]);
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+#pragma unroll
+          for (int sft = 1; sft < LANES; sft <<= 1) part[u] += __shfl_xor(part[u], sft, kWave);
+          const int64_t kk = k + u * G + g;
+          if (li == 0 && kk < ke) a.dvals[kk] = part[u];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pack: Bp[u, :] = B[uc[u], :]  (bit-exact row gather)
+// ---------------------------------------------------------------------------
+template <typename T, int LANES, int VEC, int UNROLL>
+__global__ __launch_bounds__(kBlock) void k_pack(const int32_t* __restrict__ uc, int64_t U,
+                                                 const T* __restrict__ B, int64_t ldb,
+                                                 T* __restrict__ Bp, int64_t ldp, int32_t N) {
+  constexpr int G = kWave / LANES;
+  constexpr int TW = LANES * VEC;
+  const int lane = lane_id();
+  const int g = lane / LANES;
+  const int li = lane % LANES;
+  const int64_t groups = (int64_t)gridDim.x * kWavesPerBlock * G;
+  const int64_t gid = ((int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)) * G + g;
+  for (int64_t u0 = gid; u0 < U; u0 += groups * UNROLL) {
+    int32_t src[UNROLL];
+#pragma unroll
+    for (int q = 0; q < UNROLL; ++q) {
+      const int64_t u = u0 + q * groups;
+      src[q] = u < U ? uc[u] : -1;
+    }
+    for (int64_t c = (int64_t)li * VEC; c < N; c += TW) {
+#pragma unroll
+      for (int q = 0; q < UNROLL; ++q) {
+        const int64_t u = u0 + q * groups;
+        if (src[q] >= 0) RawVec<T, VEC>::copy(B + (int64_t)src[q] * ldb + c, Bp + u * ldp + c);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one launch per column block: Y[row] += segment sum (blocks in order)
+// ---------------------------------------------------------------------------
+template <typename TIN, typename TOUT, int LANES, int VEC>
+__global__ __launch_bounds__(kBlock) void k_spmm_segments(
+    const int32_t* __restrict__ seg_row, const int32_t* __restrict__ seg_begin,
+    const int32_t* __restrict__ seg_end, int64_t s0, int64_t s1, const int32_t* __restrict__ colmap,
+    const float* __restrict__ vals, const TIN* __restrict__ X, int64_t ldx, TOUT* __restrict__ Y,
+    int64_t ldy, int32_t N, int first) {
+  constexpr int G = kWave / LANES;
+  constexpr int TW = LANES * VEC;
+  const int lane = lane_id();
+  const int g = lane / LANES;
+  const int li = lane % LANES;
+  const int64_t groups = (int64_t)gridDim.x * kWavesPerBlock * G;
+  for (int64_t s = s0 + ((int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)) * G + g; s < s1;
+       s += groups) {
+    const int32_t r = seg_row[s];
+    const int32_t kb = seg_begin[s], ke = seg_end[s];
+    for (int64_t c = (int64_t)li * VEC; c < N; c += TW) {
+      float acc[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
+      for (int32_t k = kb; k < ke; ++k) {
+        float x[VEC];
+        Elem<TIN>::template load<VEC>(X + (int64_t)colmap[k] * ldx + c, x);
+        const float v = vals[k];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e] = fmaf(v, x[e], acc[e]);
+      }
+      TOUT* o = Y + (int64_t)r * ldy + c;
+      if (!first) {
+        float cur[VEC];
+        Elem<TOUT>::template load<VEC>(o, cur);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e] += cur[e];
+      }
+      Elem<TOUT>::template store<VEC>(o, acc);
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_zero_rows(T* __restrict__ Y, int64_t rows, int64_t ldy, int32_t N) {
+  const int64_t total = rows * (int64_t)N;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / N, c = i - r * N;
+    Y[r * ldy + c] = T(0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// setup kernels: transposed pattern and per-block segments
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t row_of(const int64_t* __restrict__ ptr, int64_t rows, int64_t k) {
+  int64_t lo = 0, hi = rows - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (ptr[mid] <= k) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_iota(uint32_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (uint32_t)i;
+}
+
+// After sorting (colmap, k): row of each entry and the first entry of each
+// packed column (every packed column has at least one entry).
+__global__ void k_transpose_finish(const uint32_t* __restrict__ skeys,
+                                   const uint32_t* __restrict__ perm, int64_t nnz,
+                                   const int64_t* __restrict__ row_ptr, int64_t rows, int64_t U,
+                                   int32_t* __restrict__ trow, int64_t* __restrict__ tptr) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nnz;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    trow[j] = (int32_t)row_of(row_ptr, rows, perm[j]);
+    if (j == 0 || skeys[j] != skeys[j - 1]) tptr[skeys[j]] = j;
+    if (j == nnz - 1) tptr[U] = nnz;
+  }
+}
+
+// Segment starts: first nonzero of a row, or a change of column block.
+__global__ void k_seg_flags(const int64_t* __restrict__ row_ptr, int64_t rows,
+                            const int32_t* __restrict__ col, int64_t nnz, int64_t K,
+                            int32_t* __restrict__ flag) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    int32_t f = 1;
+    if (k > 0) {
+      const int64_t r = row_of(row_ptr, rows, k);
+      f = (row_ptr[r] == k) || ((int64_t)col[k] / K != (int64_t)col[k - 1] / K);
+    }
+    flag[k] = f;
+  }
+}
+
+__global__ void k_seg_emit(const int32_t* __restrict__ flag, const int64_t* __restrict__ pos,
+                           int64_t nnz, const int64_t* __restrict__ row_ptr, int64_t rows,
+                           const int32_t* __restrict__ col, int64_t K, uint32_t* __restrict__ key,
+                           int32_t* __restrict__ sbeg, int32_t* __restrict__ srow) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    if (!flag[k]) continue;
+    const int64_t s = pos[k];
+    sbeg[s] = (int32_t)k;
+    srow[s] = (int32_t)row_of(row_ptr, rows, k);
+    key[s] = (uint32_t)((int64_t)col[k] / K);
+  }
+}
+
+__global__ void k_seg_gather(const uint32_t* __restrict__ order, int64_t nseg,
+                             const int32_t* __restrict__ sbeg, const int32_t* __restrict__ srow,
+                             int64_t nnz, int32_t* __restrict__ obeg, int32_t* __restrict__ oend,
+                             int32_t* __restrict__ orow) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nseg;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t s = order[j];
+    obeg[j] = sbeg[s];
+    oend[j] = (s + 1 < nseg) ? sbeg[s + 1] : (int32_t)nnz;
+    orow[j] = srow[s];
+  }
+}
+
+// off[q] = first sorted segment of block q (lower bound), off[P] = nseg.
+__global__ void k_seg_off(const uint32_t* __restrict__ skey, int64_t nseg, int32_t P,
+                          int64_t* __restrict__ off) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q > P) return;
+  int64_t lo = 0, hi = nseg;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)skey[mid] < q) lo = mid + 1; else hi = mid;
+  }
+  off[q] = lo;
+}
+
+__global__ void k_fill_random_f32(float* p, int64_t n, uint64_t seed) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    p[i] = (float)((int64_t)(z >> 40) - (1ll << 23)) * (1.0f / 8388608.0f);
+  }
+}
+
+unsigned grid_for(int64_t n, int64_t cap = 65536) {
+  int64_t g = ceil_div(n > 0 ? n : 1, kBlock);
+  return (unsigned)(g < cap ? g : cap);
+}
+
+// ---------------------------------------------------------------------------
+// dispatch helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+bool aligned16(const void* p, int64_t ld) {
+  return ((uintptr_t)p % 16 == 0) && ((ld * (int64_t)sizeof(T)) % 16 == 0);
+}
+
+// Vector width in elements: 16 bytes when N, ld and base allow it, else 1.
+template <typename T>
+int vec_for(int32_t N, std::initializer_list<std::pair<const void*, int64_t>> mats) {
+  constexpr int V = Elem<T>::kVec16;
+  if (N % V) return 1;
+  for (auto& m : mats)
+    if (m.first && !aligned16<T>(m.first, m.second)) return 1;
+  return V;
+}
+
+int grid_waves(shiro_plan plan, const shiro_tuning_t& t, int32_t W, int32_t* chunks_per_wave,
+               unsigned* blocks) {
+  const int64_t max_blocks = (int64_t)plan->num_cus * (t.wg_per_cu > 0 ? t.wg_per_cu : 8);
+  int64_t nb = ceil_div(W, kWavesPerBlock);
+  if (nb > max_blocks) nb = max_blocks;
+  if (nb < 1) nb = 1;
+  *chunks_per_wave = (int32_t)ceil_div(W, nb * kWavesPerBlock);
+  nb = ceil_div(ceil_div(W, *chunks_per_wave), kWavesPerBlock);
+  if (t.xcd_remap) nb = ceil_div(nb, 8) * 8;  // whole rounds of the 8 XCDs
+  *blocks = (unsigned)nb;
+  return SHIRO_OK;
+}
+
+template <typename TIN, typename TOUT, int VEC>
+int spmm_dispatch(const shiro_tuning_t& t, dim3 grid, hipStream_t s, const SpmmArgs& a) {
+#define SHIRO_SPMM_CASE(L, U)                                                  \
+  if (t.lanes == L && t.unroll == U) {                                         \
+    k_spmm<TIN, TOUT, L, VEC, U><<<grid, kBlock, 0, s>>>(a);                   \
+    SHIRO_LAUNCH_CHECK();                                                      \
+    return SHIRO_OK;                                                           \
+  }
+  SHIRO_SPMM_CASE(8, 1) SHIRO_SPMM_CASE(8, 2) SHIRO_SPMM_CASE(8, 4)
+  SHIRO_SPMM_CASE(16, 1) SHIRO_SPMM_CASE(16, 2) SHIRO_SPMM_CASE(16, 4)
+  SHIRO_SPMM_CASE(32, 1) SHIRO_SPMM_CASE(32, 2) SHIRO_SPMM_CASE(32, 4)
+  SHIRO_SPMM_CASE(64, 1) SHIRO_SPMM_CASE(64, 2) SHIRO_SPMM_CASE(64, 4)
+#undef SHIRO_SPMM_CASE
+  return set_error(SHIRO_ERR_UNSUPPORTED, "spmm: no kernel for lanes/unroll");
+}
+
+template <typename TIN, int VEC>
+int sddmm_dispatch(const shiro_tuning_t& t, dim3 grid, hipStream_t s, const SddmmArgs& a) {
+#define SHIRO_SDDMM_CASE(L, U)                                                 \
+  if (t.lanes == L && t.unroll == U) {                                         \
+    k_sddmm<TIN, L, VEC, U><<<grid, kBlock, 0, s>>>(a);                        \
+    SHIRO_LAUNCH_CHECK();                                                      \
+    return SHIRO_OK;                                                           \
+  }
+  SHIRO_SDDMM_CASE(8, 1) SHIRO_SDDMM_CASE(8, 2) SHIRO_SDDMM_CASE(8, 4)
+  SHIRO_SDDMM_CASE(16, 1) SHIRO_SDDMM_CASE(16, 2) SHIRO_SDDMM_CASE(16, 4)
+  SHIRO_SDDMM_CASE(32, 1) SHIRO_SDDMM_CASE(32, 2) SHIRO_SDDMM_CASE(32, 4)
+  SHIRO_SDDMM_CASE(64, 1) SHIRO_SDDMM_CASE(64, 2) SHIRO_SDDMM_CASE(64, 4)
+#undef SHIRO_SDDMM_CASE
+  return set_error(SHIRO_ERR_UNSUPPORTED, "sddmm: no kernel for lanes/unroll");
+}
+
+// Lanes actually used: never more than one column tile needs.
+int effective_lanes(int lanes, int32_t N, int vec) {
+  int need = (int)ceil_div(N, vec);
+  int l = lanes;
+  while (l > 8 && l / 2 >= need) l /= 2;
+  return l;
+}
+
+template <typename TIN, typename TOUT>
+int run_spmm_family(shiro_plan plan, shiro_tuning_t t, const WorkList* wl, SpmmArgs a, int vec,
+                    hipStream_t s) {
+  t.lanes = effective_lanes(t.lanes, a.N, vec);
+  unsigned nb;
+  SHIRO_TRY(grid_waves(plan, t, wl->W, &a.chunks_per_wave, &nb));
+  const int ntiles = (int)ceil_div(a.N, (int64_t)t.lanes * vec);
+  a.xcd_remap = t.xcd_remap;
+  dim3 grid(nb, ntiles);
+  if (vec == Elem<TIN>::kVec16) {
+    SHIRO_TRY((spmm_dispatch<TIN, TOUT, Elem<TIN>::kVec16>(t, grid, s, a)));
+  } else {
+    SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1>(t, grid, s, a)));
+  }
+  const unsigned fb = grid_for((int64_t)wl->W * kWave, 4096);
+  if (vec == Elem<TIN>::kVec16 && (a.N % 4) == 0) {
+    k_fixup<TOUT, 4><<<fb, kBlock, 0, s>>>(a);
+  } else {
+    k_fixup<TOUT, 1><<<fb, kBlock, 0, s>>>(a);
+  }
+  SHIRO_LAUNCH_CHECK();
+  return SHIRO_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// host entry points
+// ===========================================================================
+int build_worklist(const int64_t* ptr, int64_t R, int64_t nnz, int32_t chunk, WorkList* wl,
+                   hipStream_t s) {
+  wl->chunk = chunk;
+  wl->W = (int32_t)ceil_div(R + nnz, chunk);
+  SHIRO_TRY(dev_alloc_n(&wl->chunk_row, (int64_t)wl->W + 1));
+  SHIRO_TRY(dev_alloc_n(&wl->chunk_nz, (int64_t)wl->W + 1));
+  k_merge_path<<<grid_for((int64_t)wl->W + 1, 1 << 20), kBlock, 0, s>>>(
+      ptr, (int32_t)R, nnz, chunk, wl->W, wl->chunk_row, wl->chunk_nz);
+  SHIRO_LAUNCH_CHECK();
+  return SHIRO_OK;
+}
+
+int build_transposed(shiro_plan plan, hipStream_t s) {
+  Transposed& tr = plan->tr;
+  if (tr.built) return SHIRO_OK;
+  const int64_t nnz = plan->nnz, U = plan->U;
+  SHIRO_TRY(dev_alloc_n(&tr.ptr, U + 1));
+  SHIRO_TRY(dev_alloc_n(&tr.row, nnz > 0 ? nnz : 1));
+  SHIRO_TRY(dev_alloc_n(&tr.perm, nnz > 0 ? nnz : 1));
+  if (nnz == 0) {
+    scan_generic(
+        [] __device__(int64_t) -> int64_t { return 0; }, 0,
+        [] __device__(int64_t, int64_t, int64_t) {}, tr.ptr, nullptr, s);
+    tr.built = true;
+    return SHIRO_OK;
+  }
+  // scratch: iota values + sorted keys + sort scratch
+  const int64_t need = 2 * (nnz * 4 + 256) + sort_scratch_bytes(nnz);
+  SHIRO_TRY(ensure_scratch(plan, need));
+  char* p = reinterpret_cast<char*>(plan->scratch);
+  uint32_t* iota = reinterpret_cast<uint32_t*>(p);
+  uint32_t* skeys = reinterpret_cast<uint32_t*>(p + (nnz * 4 + 256) / 256 * 256);
+  void* sort_tmp = p + 2 * ((nnz * 4 + 256) / 256 * 256);
+  k_iota<<<grid_for(nnz), kBlock, 0, s>>>(iota, nnz);
+  SHIRO_LAUNCH_CHECK();
+  int bits = 0;
+  while (bits < 32 && ((int64_t)1 << bits) < U) ++bits;
+  SHIRO_TRY(radix_sort_pairs(reinterpret_cast<const uint32_t*>(plan->colmap), iota, skeys,
+                             reinterpret_cast<uint32_t*>(tr.perm), nnz, bits, sort_tmp, s));
+  k_transpose_finish<<<grid_for(nnz), kBlock, 0, s>>>(skeys, reinterpret_cast<uint32_t*>(tr.perm),
+                                                       nnz, plan->row_ptr, plan->rows, U, tr.row,
+                                                       tr.ptr);
+  SHIRO_LAUNCH_CHECK();
+  SHIRO_HIP(hipStreamSynchronize(s));
+  tr.built = true;
+  return SHIRO_OK;
+}
+
+int build_segments(shiro_plan plan, hipStream_t s) {
+  BlockSegments& sg = plan->seg;
+  if (sg.built) return SHIRO_OK;
+  const int64_t nnz = plan->nnz;
+  const int32_t P = plan->P;
+  sg.h_off.assign((size_t)P + 1, 0);
+  if (nnz == 0) {
+    sg.nseg = 0;
+    sg.built = true;
+    return SHIRO_OK;
+  }
+  auto al = [](int64_t b) { return (b + 255) / 256 * 256; };
+  const int64_t need = al(nnz * 4) + al(nnz * 8) + al(8) + 3 * al(nnz * 4) + al(nnz * 4) +
+                       al(nnz * 4) + al((int64_t)(P + 1) * 8) +
+                       std::max(scan_scratch_bytes(nnz), sort_scratch_bytes(nnz));
+  SHIRO_TRY(ensure_scratch(plan, need));
+  char* p = reinterpret_cast<char*>(plan->scratch);
+  auto take = [&](int64_t b) {
+    char* r = p;
+    p += al(b);
+    return r;
+  };
+  int32_t* flag = reinterpret_cast<int32_t*>(take(nnz * 4));
+  int64_t* pos = reinterpret_cast<int64_t*>(take(nnz * 8));
+  int64_t* d_n = reinterpret_cast<int64_t*>(take(8));
+  uint32_t* key = reinterpret_cast<uint32_t*>(take(nnz * 4));
+  int32_t* sbeg = reinterpret_cast<int32_t*>(take(nnz * 4));
+  int32_t* srow = reinterpret_cast<int32_t*>(take(nnz * 4));
+  uint32_t* iota = reinterpret_cast<uint32_t*>(take(nnz * 4));
+  uint32_t* skey = reinterpret_cast<uint32_t*>(take(nnz * 4));
+  int64_t* off = reinterpret_cast<int64_t*>(take((int64_t)(P + 1) * 8));
+  void* tmp = p;
+
+  k_seg_flags<<<grid_for(nnz), kBlock, 0, s>>>(plan->row_ptr, plan->rows, plan->col, nnz, plan->K,
+                                                flag);
+  SHIRO_LAUNCH_CHECK();
+  SHIRO_TRY(exclusive_scan_i32_to_i64(flag, nnz, pos, d_n, tmp, s));
+  SHIRO_HIP(hipMemcpyAsync(plan->h_pinned, d_n, 8, hipMemcpyDeviceToHost, s));
+  SHIRO_HIP(hipStreamSynchronize(s));
+  const int64_t nseg = plan->h_pinned[0];
+  sg.nseg = nseg;
+  k_seg_emit<<<grid_for(nnz), kBlock, 0, s>>>(flag, pos, nnz, plan->row_ptr, plan->rows,
+                                               plan->col, plan->K, key, sbeg, srow);
+  SHIRO_LAUNCH_CHECK();
+  k_iota<<<grid_for(nseg), kBlock, 0, s>>>(iota, nseg);
+  SHIRO_LAUNCH_CHECK();
+  int bits = 0;
+  while (bits < 32 && ((int64_t)1 << bits) < P) ++bits;
+  uint32_t* order = reinterpret_cast<uint32_t*>(flag);  // flags no longer needed
+  SHIRO_TRY(radix_sort_pairs(key, iota, skey, order, nseg, bits, tmp, s));
+  SHIRO_TRY(dev_alloc_n(&sg.seg_row, nseg));
+  SHIRO_TRY(dev_alloc_n(&sg.seg_begin, nseg));
+  SHIRO_TRY(dev_alloc_n(&sg.seg_end, nseg));
+  k_seg_gather<<<grid_for(nseg), kBlock, 0, s>>>(order, nseg, sbeg, srow, nnz, sg.seg_begin,
+                                                  sg.seg_end, sg.seg_row);
+  SHIRO_LAUNCH_CHECK();
+  k_seg_off<<<grid_for((int64_t)P + 1), kBlock, 0, s>>>(skey, nseg, P, off);
+  SHIRO_LAUNCH_CHECK();
+  std::vector<int64_t> h((size_t)P + 1);
+  SHIRO_HIP(hipMemcpyAsync(h.data(), off, (size_t)(P + 1) * 8, hipMemcpyDeviceToHost, s));
+  SHIRO_HIP(hipStreamSynchronize(s));
+  sg.h_off = h;
+  sg.built = true;
+  return SHIRO_OK;
+}
+
+int launch_pack(shiro_plan plan, const void* B, int64_t ldb, int32_t N, shiro_dtype dt, void* Bp,
+                int64_t ldp, hipStream_t s) {
+  const int64_t U = plan->U;
+  if (U == 0 || N == 0) return SHIRO_OK;
+  const unsigned nb = grid_for(U * 8, (int64_t)plan->num_cus * 8);
+  if (dt == SHIRO_F32) {
+    const int v = vec_for<float>(N, {{B, ldb}, {Bp, ldp}});
+    const int64_t lanes = effective_lanes(64, N, v);
+    auto go = [&](auto L, auto V) {
+      k_pack<float, decltype(L)::value, decltype(V)::value, 4><<<nb, kBlock, 0, s>>>(
+          plan->unique_cols, U, (const float*)B, ldb, (float*)Bp, ldp, N);
+    };
+    if (v == 4) {
+      if (lanes <= 8) go(std::integral_constant<int, 8>{}, std::integral_constant<int, 4>{});
+      else if (lanes <= 16) go(std::integral_constant<int, 16>{}, std::integral_constant<int, 4>{});
+      else if (lanes <= 32) go(std::integral_constant<int, 32>{}, std::integral_constant<int, 4>{});
+      else go(std::integral_constant<int, 64>{}, std::integral_constant<int, 4>{});
+    } else {
+      go(std::integral_constant<int, 64>{}, std::integral_constant<int, 1>{});
+    }
+  } else {
+    const int v = vec_for<bf16_t>(N, {{B, ldb}, {Bp, ldp}});
+    const int64_t lanes = effective_lanes(64, N, v);
+    auto go = [&](auto L, auto V) {
+      k_pack<bf16_t, decltype(L)::value, decltype(V)::value, 4><<<nb, kBlock, 0, s>>>(
+          plan->unique_cols, U, (const bf16_t*)B, ldb, (bf16_t*)Bp, ldp, N);
+    };
+    if (v == 8) {
+      if (lanes <= 8) go(std::integral_constant<int, 8>{}, std::integral_constant<int, 8>{});
+      else if (lanes <= 16) go(std::integral_constant<int, 16>{}, std::integral_constant<int, 8>{});
+      else if (lanes <= 32) go(std::integral_constant<int, 32>{}, std::integral_constant<int, 8>{});
+      else go(std::integral_constant<int, 64>{}, std::integral_constant<int, 8>{});
+    } else {
+      go(std::integral_constant<int, 64>{}, std::integral_constant<int, 1>{});
+    }
+  }
+  SHIRO_LAUNCH_CHECK();
+  return SHIRO_OK;
+}
+
+int launch_spmm(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* X,
+                int64_t ldx, int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy,
+                shiro_dtype out_dt, hipStream_t s) {
+  if (plan->rows == 0 || N == 0) return SHIRO_OK;
+  const WorkList* wl;
+  SHIRO_TRY(ensure_rows_work(plan, t.chunk, !stream_capturing(s), s, &wl));
+  SHIRO_TRY(ensure_carry(plan, (int64_t)wl->W * 2 * N, !stream_capturing(s)));
+  SpmmArgs a{};
+  a.ptr = plan->row_ptr;
+  a.idx = plan->colmap;
+  a.perm = nullptr;
+  a.vals = vals + plan->nz_begin;
+  a.X = X;
+  a.ldx = ldx;
+  a.out = Y;
+  a.ldo = ldy;
+  a.chunk_row = wl->chunk_row;
+  a.chunk_nz = wl->chunk_nz;
+  a.carry = plan->carry;
+  a.W = wl->W;
+  a.R = (int32_t)plan->rows;
+  a.N = N;
+  if (in_dt == SHIRO_F32 && out_dt == SHIRO_F32) {
+    const int v = vec_for<float>(N, {{X, ldx}, {Y, ldy}});
+    return run_spmm_family<float, float>(plan, t, wl, a, v, s);
+  }
+  if (in_dt == SHIRO_BF16 && out_dt == SHIRO_F32) {
+    const int v = vec_for<bf16_t>(N, {{X, ldx}}) == 8 && aligned16<float>(Y, ldy) ? 8 : 1;
+    return run_spmm_family<bf16_t, float>(plan, t, wl, a, v, s);
+  }
+  if (in_dt == SHIRO_BF16 && out_dt == SHIRO_BF16) {
+    const int v = vec_for<bf16_t>(N, {{X, ldx}, {Y, ldy}});
+    return run_spmm_family<bf16_t, bf16_t>(plan, t, wl, a, v, s);
+  }
+  return set_error(SHIRO_ERR_UNSUPPORTED, "spmm: dtype pair not supported (F32->F32, BF16->F32, BF16->BF16)");
+}
+
+int launch_spmm_t(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* dY,
+                  int64_t lddy, int32_t N, shiro_dtype dt, void* dBp, int64_t lddbp, void* dB,
+                  int64_t lddb, hipStream_t s) {
+  if (plan->U == 0 || N == 0 || (!dBp && !dB)) return SHIRO_OK;
+  if (!plan->tr.built) {
+    if (stream_capturing(s))
+      return set_error(SHIRO_ERR_CAPTURING, "backward: transposed pattern not prepared before capture");
+    SHIRO_TRY(build_transposed(plan, s));
+  }
+  const WorkList* wl;
+  SHIRO_TRY(ensure_cols_work(plan, t.chunk, !stream_capturing(s), s, &wl));
+  SHIRO_TRY(ensure_carry(plan, (int64_t)wl->W * 2 * N, !stream_capturing(s)));
+  SpmmArgs a{};
+  a.ptr = plan->tr.ptr;
+  a.idx = plan->tr.row;
+  a.perm = plan->tr.perm;
+  a.vals = vals + plan->nz_begin;
+  a.X = dY;
+  a.ldx = lddy;
+  a.out = dBp;
+  a.ldo = lddbp;
+  a.scat = dB;
+  a.lds = lddb;
+  a.scat_idx = plan->unique_cols;
+  a.chunk_row = wl->chunk_row;
+  a.chunk_nz = wl->chunk_nz;
+  a.carry = plan->carry;
+  a.W = wl->W;
+  a.R = (int32_t)plan->U;
+  a.N = N;
+  if (dt == SHIRO_F32) {
+    const int v = vec_for<float>(N, {{dY, lddy}, {dBp, lddbp}, {dB, lddb}});
+    return run_spmm_family<float, float>(plan, t, wl, a, v, s);
+  }
+  const int v = vec_for<bf16_t>(N, {{dY, lddy}, {dBp, lddbp}, {dB, lddb}});
+  return run_spmm_family<bf16_t, bf16_t>(plan, t, wl, a, v, s);
+}
+
+int launch_sddmm(shiro_plan plan, const shiro_tuning_t& t, const float*, const void* dY,
+                 int64_t lddy, const void* Bp, int64_t ldp, int32_t N, shiro_dtype dt,
+                 float* dvals, hipStream_t s) {
+  if (plan->nnz == 0) return SHIRO_OK;
+  const WorkList* wl;
+  SHIRO_TRY(ensure_rows_work(plan, t.chunk, !stream_capturing(s), s, &wl));
+  SddmmArgs a{};
+  a.ptr = plan->row_ptr;
+  a.idx = plan->colmap;
+  a.dY = dY;
+  a.lddy = lddy;
+  a.Bp = Bp;
+  a.ldp = ldp;
+  a.dvals = dvals + plan->nz_begin;
+  a.chunk_row = wl->chunk_row;
+  a.chunk_nz = wl->chunk_nz;
+  a.W = wl->W;
+  a.R = (int32_t)plan->rows;
+  a.N = N;
+  a.xcd_remap = t.xcd_remap;
+  shiro_tuning_t tt = t;
+  unsigned nb;
+  if (dt == SHIRO_F32) {
+    const int v = vec_for<float>(N, {{dY, lddy}, {Bp, ldp}});
+    tt.lanes = effective_lanes(t.lanes, N, v);
+    SHIRO_TRY(grid_waves(plan, tt, wl->W, &a.chunks_per_wave, &nb));
+    if (v == 4) return sddmm_dispatch<float, 4>(tt, dim3(nb), s, a);
+    return sddmm_dispatch<float, 1>(tt, dim3(nb), s, a);
+  }
+  const int v = vec_for<bf16_t>(N, {{dY, lddy}, {Bp, ldp}});
+  tt.lanes = effective_lanes(t.lanes, N, v);
+  SHIRO_TRY(grid_waves(plan, tt, wl->W, &a.chunks_per_wave, &nb));
+  if (v == 8) return sddmm_dispatch<bf16_t, 8>(tt, dim3(nb), s, a);
+  return sddmm_dispatch<bf16_t, 1>(tt, dim3(nb), s, a);
+}
+
+int launch_spmm_per_block(shiro_plan plan, const float* vals, const void* X, int64_t ldx,
+                          int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy, shiro_dtype out_dt,
+                          hipStream_t s) {
+  if (plan->rows == 0 || N == 0) return SHIRO_OK;
+  if (!plan->seg.built) {
+    if (stream_capturing(s))
+      return set_error(SHIRO_ERR_CAPTURING, "per-block spmm: segments not prepared before capture");
+    SHIRO_TRY(build_segments(plan, s));
+  }
+  const float* v = vals + plan->nz_begin;
+  const auto& off = plan->seg.h_off;
+  auto run = [&](auto tin, auto tout, auto L, auto V) -> int {
+    using TIN = decltype(tin);
+    using TOUT = decltype(tout);
+    k_zero_rows<TOUT><<<grid_for(plan->rows * (int64_t)N, 65536), kBlock, 0, s>>>(
+        (TOUT*)Y, plan->rows, ldy, N);
+    SHIRO_LAUNCH_CHECK();
+    for (int32_t q = 0; q < plan->P; ++q) {
+      const int64_t s0 = off[q], s1 = off[q + 1];
+      if (s1 <= s0) continue;
+      constexpr int G = kWave / decltype(L)::value;
+      const unsigned nb = grid_for(ceil_div(s1 - s0, G) * kWave, (int64_t)plan->num_cus * 16);
+      k_spmm_segments<TIN, TOUT, decltype(L)::value, decltype(V)::value><<<nb, kBlock, 0, s>>>(
+          plan->seg.seg_row, plan->seg.seg_begin, plan->seg.seg_end, s0, s1, plan->colmap, v,
+          (const TIN*)X, ldx, (TOUT*)Y, ldy, N, 0);
+      SHIRO_LAUNCH_CHECK();
+    }
+    return SHIRO_OK;
+  };
+  using I8 = std::integral_constant<int, 8>;
+  using I4 = std::integral_constant<int, 4>;
+  using I1 = std::integral_constant<int, 1>;
+  using L32 = std::integral_constant<int, 32>;
+  using L64 = std::integral_constant<int, 64>;
+  if (in_dt == SHIRO_F32 && out_dt == SHIRO_F32) {
+    if (vec_for<float>(N, {{X, ldx}, {Y, ldy}}) == 4) return run(float{}, float{}, L32{}, I4{});
+    return run(float{}, float{}, L64{}, I1{});
+  }
+  if (in_dt == SHIRO_BF16 && out_dt == SHIRO_F32) {
+    if (vec_for<bf16_t>(N, {{X, ldx}}) == 8 && aligned16<float>(Y, ldy)) return run(bf16_t{}, float{}, L32{}, I8{});
+    return run(bf16_t{}, float{}, L64{}, I1{});
+  }
+  if (in_dt == SHIRO_BF16 && out_dt == SHIRO_BF16) {
+    if (vec_for<bf16_t>(N, {{X, ldx}, {Y, ldy}}) == 8) return run(bf16_t{}, bf16_t{}, L32{}, I8{});
+    return run(bf16_t{}, bf16_t{}, L64{}, I1{});
+  }
+  return set_error(SHIRO_ERR_UNSUPPORTED, "spmm: dtype pair not supported");
+}
+
+int launch_fill_random(float* p, int64_t n, uint64_t seed, hipStream_t s) {
+  if (n <= 0) return SHIRO_OK;
+  k_fill_random_f32<<<grid_for(n), kBlock, 0, s>>>(p, n, seed);
+  SHIRO_LAUNCH_CHECK();
+  return SHIRO_OK;
+}
+
+}  // namespace shiro

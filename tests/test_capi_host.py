@@ -1,0 +1,101 @@
+"""Host-side checks of the C-ABI library (no GPU needed, no compute calls).
+
+The library must load, export every function include/shiro.h declares, and
+reject bad arguments with the documented status codes before touching HIP.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "shiro.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return re.findall(r"SHIRO_API\s+[\w\s\*]+?\b(shiro_\w+)\s*\(", text)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2512_20178_amd import _lib
+
+    return _lib.load()
+
+
+def test_header_declares_the_path_calls():
+    names = set(declared_functions())
+    for n in ("shiro_partition", "shiro_select_rows", "shiro_pack_B", "shiro_spmm", "shiro_spmm_backward"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2512_20178_amd import _lib
+
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(names) == sorted(_lib.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (shiro_\w+)", out))
+    assert set(names) == exported  # nothing else is exported
+
+
+def test_library_is_built_for_gfx950():
+    from paper_2512_20178_amd import _lib
+
+    data = open(_lib.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+
+
+def test_version(lib):
+    assert lib.shiro_version() == 10000
+
+
+def _err(lib):
+    return lib.shiro_last_error().decode()
+
+
+def test_partition_argument_errors(lib):
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    cases = [
+        ((10, 10, 0, fake, None, 1, 0, 0, None, None), "out_plan"),
+        ((0, 10, 0, fake, None, 1, 0, 0, None, ctypes.byref(h)), "n_rows"),
+        ((10, 0, 0, fake, None, 1, 0, 0, None, ctypes.byref(h)), "n_cols"),
+        ((1 << 31, 10, 0, fake, None, 1, 0, 0, None, ctypes.byref(h)), "n_rows"),
+        ((10, 10, -1, fake, None, 1, 0, 0, None, ctypes.byref(h)), "nnz"),
+        ((10, 10, 0, None, None, 1, 0, 0, None, ctypes.byref(h)), "d_row_ptr"),
+        ((10, 10, 5, fake, None, 1, 0, 0, None, ctypes.byref(h)), "d_col"),
+        ((10, 10, 0, fake, None, 0, 0, 0, None, ctypes.byref(h)), "P < 1"),
+        ((10, 10, 0, fake, None, 4, 4, 0, None, ctypes.byref(h)), "p outside"),
+        ((10, 10, 0, fake, None, 4, -1, 0, None, ctypes.byref(h)), "p outside"),
+    ]
+    for args, frag in cases:
+        assert lib.shiro_partition(*args) == -1
+        assert frag in _err(lib)
+
+
+def test_null_plan_errors(lib):
+    P = ctypes.c_void_p(None)
+    assert lib.shiro_select_rows(P, None, None, None) == -1
+    assert lib.shiro_pack_B(P, None, 0, 0, 0, None, 0, None) == -1
+    assert lib.shiro_spmm(P, None, None, 0, 0, 0, None, 0, 0, 0, None) == -1
+    assert lib.shiro_spmm_backward(P, None, None, 0, None, 0, 0, 0, None, 0, None, 0, None, None) == -1
+    assert lib.shiro_prepare(P, 1, 0, 1, None) == -1
+    assert lib.shiro_autotune(P, 1, 0, 1, None) == -1
+    assert lib.shiro_plan_info(P, None) == -1
+    assert lib.shiro_copy_selection(P, None, None, None, None) == -1
+    assert lib.shiro_graph_launch(P, 0, None) == -1
+    assert lib.shiro_plan_destroy(P) == 0  # NULL is accepted
+
+
+def test_tuning_validation(lib):
+    from paper_2512_20178_amd import _lib
+
+    t = _lib.Tuning(chunk=256, lanes=64, unroll=2, hot_rows=0, xcd_remap=0, wg_per_cu=8)
+    assert lib.shiro_set_tuning(ctypes.c_void_p(None), 0, 128, 0, ctypes.byref(t)) == -1

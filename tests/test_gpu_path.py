@@ -1,0 +1,246 @@
+"""GPU parity of the HIP path against the FP64 oracle (small and medium sizes).
+
+Every case runs partition -> select_rows -> pack_B -> spmm -> spmm_backward
+through the C ABI (via the ctypes binding) and compares element by element:
+indices, offsets and packed bytes bit-exactly; float32 outputs within 1e-5
+and bfloat16 outputs within 1e-2 of the oracle, relative to the oracle's
+absolute product (|A||B|, |A|^T|dY|, sum |dY||B|) entry by entry.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-5
+TOL_BF16 = 1e-2
+
+
+@pytest.fixture(scope="module")
+def shiro():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2512_20178_amd as s
+
+    s._lib.load()  # fails loudly if the library is missing
+    return s
+
+
+def bf16_to_f32(t: torch.Tensor) -> np.ndarray:
+    return t.float().cpu().numpy()
+
+
+def make_case(name):
+    """(SparseInput, N) for a named small case."""
+    if name == "config1_rmat12":
+        return synth.config1(), 32
+    if name == "rmat12_P8_p0":
+        return synth.small_rmat(12, 16, P=8, p=0), 128
+    if name == "rmat11_P7_p6_ragged":
+        return synth.small_rmat(11, 8, P=7, p=6), 64
+    if name == "rmat10_P3_N3_scalar":
+        return synth.small_rmat(10, 4, P=3, p=1, vals_lo=-1.0), 3
+    if name == "rmat12_P16_N256":
+        return synth.small_rmat(12, 8, P=16, p=5), 256
+    if name == "rmat11_N384_multitile":
+        return synth.small_rmat(11, 8, P=2, p=0), 384
+    if name == "empty_panel":
+        return synth.from_dense_pattern(np.zeros((9, 9)), P=2, p=1), 8
+    if name == "hub_row":
+        rng = np.random.default_rng(5)
+        n = 40000
+        m = np.zeros((64, n), np.float32)
+        m[0, rng.choice(n, 30000, replace=False)] = rng.uniform(-1, 1, 30000)  # one very long row
+        m[5, :] = 0.5  # a full row
+        m[7, rng.choice(n, 300, replace=False)] = 1.0
+        rows, cols = np.nonzero(m)
+        rp = np.zeros(65, np.int64)
+        np.cumsum(np.bincount(rows, minlength=64), out=rp[1:])
+        A = synth.SparseInput("hub", 64, n, torch.from_numpy(rp), torch.from_numpy(cols.astype(np.int32)),
+                              torch.from_numpy(m[rows, cols]), 1, 0)
+        return A, 128
+    if name == "rect_empty_block":
+        rng = np.random.default_rng(9)
+        mask = rng.random((300, 1000)) < 0.02
+        mask[:, 250:500] = False  # an empty column block
+        mask[150:300, 0:250] = True  # a dense block
+        vals = rng.uniform(0.1, 1, size=(300, 1000)).astype(np.float32) * mask
+        return synth.from_dense_pattern(vals, P=4, p=1, name="rect"), 64
+    raise KeyError(name)
+
+
+CASES = ["config1_rmat12", "rmat12_P8_p0", "rmat11_P7_p6_ragged", "rmat10_P3_N3_scalar",
+         "rmat12_P16_N256", "rmat11_N384_multitile", "empty_panel", "hub_row", "rect_empty_block"]
+
+
+class Run:
+    """One case run through the GPU path plus its oracle references."""
+
+    def __init__(self, shiro, name):
+        A, N = make_case(name)
+        self.A, self.N = A, N
+        self.dev = torch.device("cuda")
+        self.Ad = A.to(self.dev)
+        self.Ac = oracle.Csr.from_synth(A)
+        self.plan = shiro.partition(self.Ad.row_ptr, self.Ad.col, A.n_rows, A.n_cols, A.P, A.p, check=True)
+        self.U, self.Uq = shiro.select_rows(self.plan)
+        self.B = synth.dense(A.n_cols, N, 0, synth.STREAM_B)
+        self.G = synth.dense(max(self.Ac.M, 1), N, 0, synth.STREAM_DY)[: self.Ac.M]
+        self.uc, self.off, self.cm = oracle.select(self.Ac)
+
+
+@pytest.fixture(scope="module", params=CASES)
+def run(request, shiro):
+    return Run(shiro, request.param)
+
+
+def test_partition_and_block_nnz(shiro, run):
+    inf = run.plan.info()
+    Ac = run.Ac
+    assert (inf["row_begin"], inf["rows"], inf["K"]) == (Ac.row_begin, Ac.M, Ac.K)
+    assert (inf["nz_begin"], inf["nnz"]) == (Ac.nz_begin, Ac.nnz_panel)
+    assert np.array_equal(shiro.block_nnz(run.plan).cpu().numpy(), oracle.block_nnz(Ac))
+
+
+def test_select_bit_exact(shiro, run):
+    uc, off, cm = (t.cpu().numpy() for t in shiro.selection(run.plan))
+    assert run.U == len(run.uc)
+    assert run.Uq == list(np.diff(run.off))
+    assert np.array_equal(uc, run.uc)
+    assert np.array_equal(off, run.off)
+    assert np.array_equal(cm, run.cm)
+
+
+def test_pack_bit_exact(shiro, run):
+    Bp = shiro.pack_B(run.plan, run.B.to(run.dev))
+    ref = oracle.pack(run.B.numpy(), run.uc)
+    assert Bp.cpu().numpy().tobytes() == ref.tobytes()
+    Bh = run.B.to(torch.bfloat16)
+    Bph = shiro.pack_B(run.plan, Bh.to(run.dev))
+    refh = oracle.pack(Bh.view(torch.int16).numpy(), run.uc)
+    assert Bph.cpu().view(torch.int16).numpy().tobytes() == refh.tobytes()
+    # strided source and destination (leading dimensions > N)
+    Bw = torch.zeros(run.A.n_cols, run.N + 5, device=run.dev)
+    Bw[:, : run.N] = run.B.to(run.dev)
+    out = torch.full((run.U, run.N + 3), -7.0, device=run.dev)
+    shiro.pack_B(run.plan, Bw[:, : run.N], out=out[:, : run.N])
+    o = out.cpu().numpy()
+    assert o[:, : run.N].tobytes() == ref.tobytes() and np.all(o[:, run.N:] == -7.0)
+
+
+def _fwd_ref(run, B):
+    Y = oracle.spmm(run.Ac, B, None)
+    den = oracle.spmm(run.Ac, B, None, abs_mode=True)
+    return Y, den
+
+
+@pytest.mark.parametrize("mode", ["batched", "per_block"])
+def test_spmm_f32(shiro, run, mode):
+    Bp = shiro.pack_B(run.plan, run.B.to(run.dev))
+    Y = shiro.spmm(run.plan, run.Ad.vals, Bp, mode=mode)
+    Yref, den = _fwd_ref(run, run.B.numpy())
+    err = oracle.rel_err(Y.cpu().numpy(), Yref, den)
+    assert err <= TOL_F32, err
+    # run-to-run determinism
+    Y2 = shiro.spmm(run.plan, run.Ad.vals, Bp, mode=mode)
+    assert torch.equal(Y, Y2)
+
+
+def test_spmm_bf16(shiro, run):
+    Bh = run.B.to(torch.bfloat16).to(run.dev)
+    Bp = shiro.pack_B(run.plan, Bh)
+    Yf = shiro.spmm(run.plan, run.Ad.vals, Bp, out_dtype=torch.float32)
+    Yh = shiro.spmm(run.plan, run.Ad.vals, Bp, out_dtype=torch.bfloat16)
+    Yh2 = shiro.spmm(run.plan, run.Ad.vals, Bp, out_dtype=torch.bfloat16, mode="per_block")
+    Yref, den = _fwd_ref(run, run.B.numpy())  # end to end: FP64 on the original FP32 B
+    for Y in (Yf, Yh, Yh2):
+        assert oracle.rel_err(bf16_to_f32(Y), Yref, den) <= TOL_BF16
+    # kernel only: FP64 on the bf16-rounded inputs, float32 accumulation error only
+    Bq = Bh.float().cpu().numpy()
+    Yq, denq = _fwd_ref(run, Bq)
+    assert oracle.rel_err(Yf.cpu().numpy(), Yq, denq) <= TOL_F32
+    assert oracle.rel_err(bf16_to_f32(Yh), Yq, denq) <= 2.0 ** -8 + TOL_F32
+
+
+def _bwd_refs(run, B, G):
+    Ac = run.Ac
+    dBp = oracle.spmm_t(Ac, G, run.cm, n_out=run.U)
+    dBp_den = oracle.spmm_t(Ac, G, run.cm, n_out=run.U, abs_mode=True)
+    dv = oracle.sddmm(Ac, G, B, None)
+    dv_den = oracle.sddmm(Ac, G, B, None, abs_mode=True)
+    return dBp, dBp_den, dv, dv_den
+
+
+def test_backward_f32(shiro, run):
+    dev = run.dev
+    Bp = shiro.pack_B(run.plan, run.B.to(dev))
+    dY = run.G.to(dev)
+    dBp = torch.empty(run.U, run.N, device=dev)
+    base = torch.randn(run.A.n_cols, run.N, generator=torch.Generator().manual_seed(3))
+    dB = base.to(dev)  # add-scatter on top of existing values
+    dvals = torch.zeros(run.A.nnz, device=dev)
+    shiro.spmm_backward(run.plan, run.Ad.vals, dY, Bp, dBpacked=dBp, dB=dB, dvals=dvals)
+    rdBp, rden, rdv, rdv_den = _bwd_refs(run, run.B.numpy(), run.G.numpy())
+    assert oracle.rel_err(dBp.cpu().numpy(), rdBp, rden) <= TOL_F32
+    full = base.numpy().astype(np.float64)
+    full[run.uc] += rdBp
+    fden = np.abs(base.numpy()).astype(np.float64)
+    fden[run.uc] += rden
+    got = dB.cpu().numpy()
+    assert oracle.rel_err(got, full, np.maximum(fden, 1e-300)) <= TOL_F32
+    mask = np.ones(run.A.n_cols, bool)
+    mask[run.uc] = False
+    assert np.array_equal(got[mask], base.numpy()[mask])  # rows outside Cols untouched
+    gv = dvals.cpu().numpy()[run.Ac.nz_begin:run.Ac.nz_begin + run.Ac.nnz_panel]
+    assert oracle.rel_err(gv, rdv, rdv_den) <= TOL_F32
+    # determinism of every output
+    dBp2 = torch.empty_like(dBp)
+    dvals2 = torch.zeros_like(dvals)
+    shiro.spmm_backward(run.plan, run.Ad.vals, dY, Bp, dBpacked=dBp2, dvals=dvals2)
+    assert torch.equal(dBp, dBp2) and torch.equal(dvals, dvals2)
+
+
+def test_backward_bf16(shiro, run):
+    dev = run.dev
+    Bh = run.B.to(torch.bfloat16)
+    Gh = run.G.to(torch.bfloat16)
+    Bp = shiro.pack_B(run.plan, Bh.to(dev))
+    dBp = torch.empty(run.U, run.N, dtype=torch.bfloat16, device=dev)
+    dB = torch.zeros(run.A.n_cols, run.N, dtype=torch.bfloat16, device=dev)
+    dvals = torch.zeros(run.A.nnz, device=dev)
+    shiro.spmm_backward(run.plan, run.Ad.vals, Gh.to(dev), Bp, dBpacked=dBp, dB=dB, dvals=dvals)
+    rdBp, rden, rdv, rdv_den = _bwd_refs(run, run.B.numpy(), run.G.numpy())
+    assert oracle.rel_err(bf16_to_f32(dBp), rdBp, rden) <= TOL_BF16
+    assert oracle.rel_err(bf16_to_f32(dB)[run.uc], rdBp, rden) <= TOL_BF16
+    gv = dvals.cpu().numpy()[run.Ac.nz_begin:run.Ac.nz_begin + run.Ac.nnz_panel]
+    assert oracle.rel_err(gv, rdv, rdv_den) <= TOL_BF16
+
+
+@pytest.mark.parametrize("knobs", [
+    dict(chunk=16, lanes=8, unroll=1),
+    dict(chunk=64, lanes=64, unroll=4),
+    dict(chunk=1024, lanes=16, unroll=2, xcd_remap=1, wg_per_cu=2),
+    dict(chunk=4096, lanes=32, unroll=4, wg_per_cu=1),
+])
+def test_tunings_all_correct(shiro, run, knobs):
+    """Small chunks split rows over many wavefronts (carry + fix-up path)."""
+    for k in ("spmm", "spmm_t", "sddmm"):
+        shiro.set_tuning(run.plan, k, run.N, torch.float32, **knobs)
+    dev = run.dev
+    Bp = shiro.pack_B(run.plan, run.B.to(dev))
+    Y = shiro.spmm(run.plan, run.Ad.vals, Bp)
+    Yref, den = _fwd_ref(run, run.B.numpy())
+    assert oracle.rel_err(Y.cpu().numpy(), Yref, den) <= TOL_F32
+    dBp = torch.empty(run.U, run.N, device=dev)
+    dvals = torch.zeros(run.A.nnz, device=dev)
+    shiro.spmm_backward(run.plan, run.Ad.vals, run.G.to(dev), Bp, dBpacked=dBp, dvals=dvals)
+    rdBp, rden, rdv, rdv_den = _bwd_refs(run, run.B.numpy(), run.G.numpy())
+    assert oracle.rel_err(dBp.cpu().numpy(), rdBp, rden) <= TOL_F32
+    gv = dvals.cpu().numpy()[run.Ac.nz_begin:run.Ac.nz_begin + run.Ac.nnz_panel]
+    assert oracle.rel_err(gv, rdv, rdv_den) <= TOL_F32
+    for k in ("spmm", "spmm_t", "sddmm"):  # back to the defaults for other tests
+        shiro.set_tuning(run.plan, k, run.N, torch.float32, chunk=256 if k != "sddmm" else 512, lanes=64,
+                         unroll=2, xcd_remap=0, wg_per_cu=8)
