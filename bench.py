@@ -1,0 +1,336 @@
+#!/usr/bin/env python3
+"""Benchmark of the per-rank, column-based SpMM path on one MI355X.
+
+A step is one pass of the whole path over the workload: select (the
+selection kernels, re-run on the device), pack_B, spmm (all column blocks in
+one launch) and spmm_backward (dBpacked, add-scatter into dB, dvals),
+captured once in a HIP graph and replayed.  Inputs are resident in HBM
+before timing starts.  The metric counts 2*nnz*N flops for each of the three
+products of a step (Y, dBpacked, dvals).
+
+Default workload: panel 0 of a 2^24-vertex R-MAT (a/b/c/d .57/.19/.19/.05,
+32 samples per row) split into P = 128 column blocks, N = 128, float32.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload NAME] [--N 128]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="rmat24_p128_panel0",
+                    choices=["rmat24_p128_panel0", "er24_p128_panel0", "rmat12_ef16", "rmat22_ef64",
+                             "gcn_rmat21_ef25"])
+    ap.add_argument("--N", type=int, default=None)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"])
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip per-block / bf16 / parity extras")
+    ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--cpu-sample-rows", type=int, default=None)
+    return ap.parse_args()
+
+
+def make_workload(name, dev):
+    import synth
+
+    if name == "rmat24_p128_panel0":
+        return synth.config2(device=dev), 128
+    if name == "er24_p128_panel0":
+        return synth.config3_er(device=dev), 128
+    if name == "rmat12_ef16":
+        return synth.config1(device=dev), 32
+    if name == "rmat22_ef64":
+        return synth.config4(device=dev), 256
+    if name == "gcn_rmat21_ef25":
+        return synth.config5(device=dev), 128
+    raise KeyError(name)
+
+
+def src_hash(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2512_20178_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU: the per-rank path has no collectives; "
+                                   "run with --gpus 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2512_20178_amd as shiro
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    A, N0 = make_workload(args.workload, dev)
+    N = args.N or N0
+    tdt = torch.float32 if args.dtype == "f32" else torch.bfloat16
+    B = synth.dense(A.n_cols, N, 0, synth.STREAM_B, device=dev).to(tdt)
+    torch.cuda.synchronize()
+    log(f"workload {args.workload}: n={A.n_rows} nnz={A.nnz} P={A.P} N={N} generated in {time.perf_counter() - t0:.1f}s")
+
+    # ---- setup: partition + select (pattern-only, reused by every step) ----
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plan = shiro.partition(A.row_ptr, A.col, A.n_rows, A.n_cols, A.P, A.p)
+    t_part = time.perf_counter() - t
+    t = time.perf_counter()
+    U, Uq = shiro.select_rows(plan)
+    t_sel = time.perf_counter() - t
+    info = plan.info()
+    M, nnz = info["rows"], info["nnz"]
+    G = synth.dense(M, N, 0, synth.STREAM_DY, device=dev).to(tdt)
+    log(f"plan: rows={M} nnz={nnz} U={U}; partition {t_part * 1e3:.1f} ms, select {t_sel * 1e3:.1f} ms")
+
+    if not args.no_autotune:
+        t = time.perf_counter()
+        shiro.autotune(plan, N, tdt, ops=("spmm", "backward"))
+        log(f"autotune {time.perf_counter() - t:.1f}s: spmm {shiro.get_tuning(plan, 'spmm', N, tdt)} "
+            f"spmm_t {shiro.get_tuning(plan, 'spmm_t', N, tdt)} sddmm {shiro.get_tuning(plan, 'sddmm', N, tdt)}")
+    shiro.prepare(plan, N, tdt, ops=("spmm", "backward", "per_block"))
+
+    vals = A.vals
+    Bp = torch.empty(U, N, dtype=tdt, device=dev)
+    Y = torch.empty(M, N, dtype=tdt, device=dev)
+    dBp = torch.empty(U, N, dtype=tdt, device=dev)
+    dB = torch.zeros(A.n_cols, N, dtype=tdt, device=dev)
+    dvals = torch.zeros(A.nnz, dtype=torch.float32, device=dev)
+
+    def step():
+        shiro.refresh_selection(plan)
+        shiro.pack_B(plan, B, out=Bp)
+        shiro.spmm(plan, vals, Bp, out=Y)
+        shiro.spmm_backward(plan, vals, G, Bp, dBpacked=dBp, dB=dB, dvals=dvals)
+
+    # ---- capture one step as a HIP graph ----
+    cs = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with plan.capture(cs) as gid_holder:
+        step()
+    gid = gid_holder[0]
+    torch.cuda.synchronize()
+
+    with torch.cuda.stream(cs):
+        for _ in range(args.warmup):
+            plan.replay(gid, stream=cs)
+        cs.synchronize()
+        torch.cuda.synchronize()  # barrier (single rank) + device sync
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record(cs)
+        for _ in range(args.steps):
+            plan.replay(gid, stream=cs)
+        e1.record(cs)
+        cs.synchronize()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+    ms_step = e0.elapsed_time(e1) / args.steps
+    flops_step = 3 * 2.0 * nnz * N
+    gflops = flops_step / (ms_step * 1e-3) / 1e9
+    log(f"step {ms_step * 1e3:.1f} us (wall {wall / args.steps * 1e6:.1f} us) -> {gflops:.1f} GFLOP/s")
+
+    # ---- per-kernel durations on the launch stream (HIP events) ----
+    sz = 4 if tdt == torch.float32 else 2
+    rp = A.row_ptr[info["row_begin"]: info["row_begin"] + M + 1]
+    R_nonempty = int((rp[1:] != rp[:-1]).sum().item())
+    alg = {
+        "select": 8 * nnz + 4 * U + 2 * ((A.n_cols + 7) // 8),
+        "pack_B": 2 * U * N * sz,
+        "spmm": 8 * (M + 1) + 8 * nnz + U * N * sz + M * N * sz,
+        "spmm_t": 8 * (U + 1) + 8 * nnz + R_nonempty * N * sz + U * N * sz + 2 * U * N * sz,
+        "sddmm": 8 * (M + 1) + 8 * nnz + R_nonempty * N * sz + U * N * sz,
+    }
+    ops = {
+        "select": lambda: shiro.refresh_selection(plan),
+        "pack_B": lambda: shiro.pack_B(plan, B, out=Bp),
+        "spmm": lambda: shiro.spmm(plan, vals, Bp, out=Y),
+        "spmm_t": lambda: shiro.spmm_backward(plan, vals, G, None, dBpacked=dBp, dB=dB),
+        "sddmm": lambda: shiro.spmm_backward(plan, vals, G, Bp, dvals=dvals),
+    }
+    reps = 10
+    kern_us = {}
+    for name, fn in ops.items():
+        fn()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        s = torch.cuda.current_stream()
+        for a, b in evs:
+            a.record(s)
+            fn()
+            b.record(s)
+        torch.cuda.synchronize()
+        kern_us[name] = float(np.mean([a.elapsed_time(b) for a, b in evs]) * 1e3)
+    log("per-call us: " + ", ".join(f"{k}={v:.1f}" for k, v in kern_us.items()))
+    alg_step = alg["select"] + alg["pack_B"] + alg["spmm"] + alg["spmm_t"] + alg["sddmm"]
+
+    dom = max(("pack_B", "spmm", "spmm_t", "sddmm"), key=lambda k: kern_us[k])
+    achieved = alg[dom] / (kern_us[dom] * 1e-6) / 1e9
+    traffic = None
+    pmc_path = os.path.join(ROOT, "profiles", f"pmc_{dom}_{args.workload}_N{N}_{args.dtype}.json")
+    if os.path.exists(pmc_path):
+        with open(pmc_path) as f:
+            pmc = json.load(f)
+        if pmc.get("src_hash") == src_hash("spmm.hip", "common.hpp"):
+            traffic = pmc.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes": int(alg[dom]), "duration_us": round(kern_us[dom], 2)}
+
+    out = {
+        "metric": "local SpMM GFLOP/s & % HBM peak; BF16/batched/fwd+bwd vs plain FP32",
+        "value": round(gflops, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": A.n_rows, "P": A.P, "p": A.p, "rows": M, "nnz": nnz,
+                   "U": U, "N": N, "step": "select+pack_B+spmm+spmm_backward(dBpacked,dB,dvals)"},
+        "roofline": roofline,
+        "step_hbm_frac": round(alg_step / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "kernels_us": {k: round(v, 2) for k, v in kern_us.items()},
+        "kernels_hbm_frac": {k: round(alg[k] / (kern_us[k] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) for k in kern_us},
+        "setup_ms": {"partition": round(t_part * 1e3, 2), "select_rows": round(t_sel * 1e3, 2)},
+    }
+
+    if args.calib_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    if not args.no_extras:
+        # batched (one launch, row-merged) vs one launch per column block
+        def timed(fn, n=5):
+            fn()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(n):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            return a.elapsed_time(b) / n * 1e3
+
+        t_pb = timed(lambda: shiro.spmm(plan, vals, Bp, out=Y, mode="per_block"))
+        out["per_block_spmm_us"] = round(t_pb, 2)
+        out["batched_speedup"] = round(t_pb / kern_us["spmm"], 3)
+        fwd_us = kern_us["select"] + kern_us["pack_B"] + kern_us["spmm"]
+        out["fwd_gflops"] = round(2.0 * nnz * N / (fwd_us * 1e-6) / 1e9, 2)
+        out["fwd_bwd_over_fwd"] = round(ms_step * 1e3 / fwd_us, 3)
+        if tdt == torch.float32:
+            # same step with bfloat16 storage (B, Y, dY, dBpacked, dB), float32 arithmetic
+            Bh = B.to(torch.bfloat16)
+            Gh = G.to(torch.bfloat16)
+            shiro.prepare(plan, N, torch.bfloat16, ops=("spmm", "backward"))
+            Bph = torch.empty(U, N, dtype=torch.bfloat16, device=dev)
+            Yh = torch.empty(M, N, dtype=torch.bfloat16, device=dev)
+            dBph = torch.empty(U, N, dtype=torch.bfloat16, device=dev)
+            dBh = torch.zeros(A.n_cols, N, dtype=torch.bfloat16, device=dev)
+
+            def step_bf16():
+                shiro.refresh_selection(plan)
+                shiro.pack_B(plan, Bh, out=Bph)
+                shiro.spmm(plan, vals, Bph, out=Yh)
+                shiro.spmm_backward(plan, vals, Gh, Bph, dBpacked=dBph, dB=dBh, dvals=dvals)
+
+            t_bf = timed(step_bf16)
+            out["bf16_step_us"] = round(t_bf, 2)
+            out["bf16_speedup"] = round(ms_step * 1e3 / t_bf, 3)
+            del Bh, Gh, Bph, Yh, dBph, dBh
+        # sampled parity of Y at full size against the FP64 oracle
+        import oracle
+
+        Ac = host_csr(A)
+        Bh_host = B.float().cpu().numpy()
+        rpn = Ac.row_ptr[Ac.row_begin:Ac.row_end + 1]
+        rows = np.unique(np.concatenate([np.arange(0, M, max(1, M // 256)), [int(np.argmax(np.diff(rpn)))]]))
+        yref = oracle.spmm_rows(Ac, rows, Bh_host, None)
+        den = oracle.spmm_rows(Ac, rows, Bh_host, None, abs_mode=True)
+        shiro.refresh_selection(plan)
+        shiro.spmm(plan, vals, shiro.pack_B(plan, B, out=Bp), out=Y)
+        ygot = Y.float()[torch.from_numpy(rows).to(dev)].cpu().numpy()
+        out["parity_sampled_rows"] = int(len(rows))
+        out["parity_max_rel_err"] = float(oracle.rel_err(ygot, yref, den))
+        del Bh_host
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(A, B, G, N, args, out)
+
+    print(json.dumps(out), flush=True)
+
+
+def host_csr(A):
+    import oracle
+
+    return oracle.Csr(A.n_rows, A.n_cols, A.row_ptr.cpu().numpy(), A.col.cpu().numpy(), A.vals.cpu().numpy(),
+                      A.P, A.p)
+
+
+def cpu_baseline(A, B, G, N, args, out):
+    """The FP64 oracle on the host cores: select, pack, spmm, A^T dY and
+    dvals.  The sample is the whole panel when it has at most 6M nonzeros
+    (about 10-30 s of oracle work), else the leading rows of the panel up to
+    6M nonzeros (only for one-block workloads, P = 1)."""
+    import numpy as np
+
+    import oracle
+
+    Ac = host_csr(A)
+    if Ac.nnz_panel > 6_000_000:
+        assert A.P == 1, "row samples are taken of one-block workloads only"
+        rp = Ac.row_ptr
+        r1 = int(np.searchsorted(rp, rp[Ac.row_begin] + 6_000_000))
+        Ac = oracle.Csr(r1, A.n_cols, rp[: r1 + 1], Ac.col[: rp[r1]], Ac.vals[: rp[r1]], 1, 0)
+    Bh = B.float().cpu().numpy()
+    Gh = G[: Ac.M].float().cpu().numpy()
+    t = time.perf_counter()
+    uc, off, cm = oracle.select(Ac)
+    Bp = oracle.pack(Bh, uc)
+    oracle.spmm(Ac, Bp, cm)
+    oracle.spmm_t(Ac, Gh, cm, n_out=len(uc))
+    oracle.sddmm(Ac, Gh, Bp, cm)
+    dt = time.perf_counter() - t
+    flops = 3 * 2.0 * Ac.nnz_panel * N
+    return {"value": round(flops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"rows [{Ac.row_begin},{Ac.row_end}) of {args.workload} ({Ac.nnz_panel} nonzeros, "
+                      f"P={Ac.P}, N={N}): select+pack+spmm+A^T dY+dvals in FP64, one run, {dt:.2f} s",
+            "seconds": round(dt, 3)}
+
+
+if __name__ == "__main__":
+    main()

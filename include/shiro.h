@@ -169,6 +169,13 @@ SHIRO_API int shiro_block_nnz(shiro_plan plan, int64_t* d_block_nnz, shiro_strea
 SHIRO_API int shiro_select_rows(shiro_plan plan, shiro_stream_t stream, int64_t* h_U_total,
                                 int64_t* h_U_per_block);
 
+/* Re-run the selection kernels of select_rows into the plan's arrays without
+ * synchronising or allocating (the pattern is the plan's own copy, so the
+ * result and U are unchanged).  Stream-ordered and capturable; lets a caller
+ * time or graph-capture the whole path including the selection step.
+ * NOT_READY before the first select_rows. */
+SHIRO_API int shiro_refresh_selection(shiro_plan plan, shiro_stream_t stream);
+
 /* Device views of the selection (owned by the plan; valid until destroy).
  * Any output pointer may be NULL.  NOT_READY before select_rows. */
 SHIRO_API int shiro_plan_selection(shiro_plan plan, const int32_t** d_unique_cols,

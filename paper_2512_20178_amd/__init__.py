@@ -23,6 +23,7 @@ __all__ = [
     "partition",
     "select_rows",
     "selection",
+    "refresh_selection",
     "block_nnz",
     "pack_B",
     "spmm",
@@ -151,6 +152,11 @@ def select_rows(plan: Plan, stream=None) -> Tuple[int, list]:
     per = (ctypes.c_int64 * P)()
     _lib.check(_L().shiro_select_rows(plan.handle, ctypes.c_void_p(_stream(stream)), ctypes.byref(U), per))
     return U.value, list(per)
+
+
+def refresh_selection(plan: Plan, stream=None):
+    """Re-run the selection kernels (stream-ordered, no sync; capturable)."""
+    _lib.check(_L().shiro_refresh_selection(plan.handle, ctypes.c_void_p(_stream(stream))))
 
 
 def selection(plan: Plan, stream=None):

@@ -50,6 +50,7 @@ EXPORTS = [
     "shiro_plan_info",
     "shiro_block_nnz",
     "shiro_select_rows",
+    "shiro_refresh_selection",
     "shiro_plan_selection",
     "shiro_copy_selection",
     "shiro_pack_B",
@@ -127,6 +128,7 @@ def load(path: str = LIB_PATH):
         L.shiro_plan_info.argtypes = [_p, ctypes.POINTER(PlanInfo)]
         L.shiro_block_nnz.argtypes = [_p, _p, _p]
         L.shiro_select_rows.argtypes = [_p, _p, ctypes.POINTER(_i64), _p]
+        L.shiro_refresh_selection.argtypes = [_p, _p]
         L.shiro_plan_selection.argtypes = [_p, ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]
         L.shiro_copy_selection.argtypes = [_p, _p, _p, _p, _p]
         L.shiro_pack_B.argtypes = [_p, _p, _i64, _i32, ctypes.c_int, _p, _i64, _p]

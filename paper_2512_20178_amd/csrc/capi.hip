@@ -97,6 +97,18 @@ int ensure_carry(shiro_plan plan, int64_t elems, bool allocate) {
   return SHIRO_OK;
 }
 
+int ensure_acc32(shiro_plan plan, int64_t elems, bool allocate) {
+  if (plan->acc32_elems >= elems) return SHIRO_OK;
+  if (!allocate) return set_error(SHIRO_ERR_CAPTURING, "per-block accumulator not prepared before capture");
+  SHIRO_HIP(hipDeviceSynchronize());
+  dev_free(plan->acc32);
+  plan->acc32 = nullptr;
+  plan->acc32_elems = 0;
+  SHIRO_TRY(dev_alloc_n(&plan->acc32, elems));
+  plan->acc32_elems = elems;
+  return SHIRO_OK;
+}
+
 shiro_tuning_t default_tuning(int kernel, int32_t, shiro_dtype) {
   shiro_tuning_t t;
   t.chunk = kernel == SHIRO_KERNEL_SDDMM ? 512 : 256;
@@ -162,6 +174,7 @@ static void plan_free(shiro_plan plan) {
   dev_free(plan->seg.seg_begin);
   dev_free(plan->seg.seg_end);
   dev_free(plan->carry);
+  dev_free(plan->acc32);
   dev_free(plan->scratch);
   if (plan->h_pinned) (void)hipHostFree(plan->h_pinned);
   delete plan;
@@ -433,12 +446,18 @@ SHIRO_API int shiro_select_rows(shiro_plan plan, shiro_stream_t stream, int64_t*
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (!plan->selected) {
     if (stream_capturing(s)) return set_error(SHIRO_ERR_CAPTURING, "select_rows: stream is capturing");
-    SHIRO_TRY(run_select(plan, s));
+    SHIRO_TRY(run_select(plan, s, true));
   }
   if (h_U_total) *h_U_total = plan->U;
   if (h_U_per_block)
     for (int32_t q = 0; q < plan->P; ++q) h_U_per_block[q] = plan->h_block_off[q + 1] - plan->h_block_off[q];
   return SHIRO_OK;
+}
+
+SHIRO_API int shiro_refresh_selection(shiro_plan plan, shiro_stream_t stream) {
+  if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "refresh_selection: plan is NULL");
+  if (!plan->selected) return set_error(SHIRO_ERR_NOT_READY, "refresh_selection: call shiro_select_rows first");
+  return run_select(plan, reinterpret_cast<hipStream_t>(stream), false);
 }
 
 SHIRO_API int shiro_plan_selection(shiro_plan plan, const int32_t** d_unique_cols,
@@ -546,7 +565,10 @@ SHIRO_API int shiro_prepare(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t
     const shiro_tuning_t t2 = tuning_for(plan, SHIRO_KERNEL_SDDMM, N, dt);
     SHIRO_TRY(ensure_rows_work(plan, t2.chunk, true, s, &wl));
   }
-  if (ops & SHIRO_OP_PER_BLOCK) SHIRO_TRY(build_segments(plan, s));
+  if (ops & SHIRO_OP_PER_BLOCK) {
+    SHIRO_TRY(build_segments(plan, s));
+    if (dt == SHIRO_BF16) SHIRO_TRY(ensure_acc32(plan, plan->rows * (int64_t)N, true));
+  }
   SHIRO_HIP(hipStreamSynchronize(s));
   return SHIRO_OK;
 }

@@ -79,6 +79,10 @@ struct shiro_plan_s {
   float* carry = nullptr;
   int64_t carry_elems = 0;
 
+  // float32 accumulator of the per-block mode when Y is bfloat16
+  float* acc32 = nullptr;
+  int64_t acc32_elems = 0;
+
   // scratch for scans and sorts
   void* scratch = nullptr;
   int64_t scratch_bytes = 0;
@@ -116,7 +120,9 @@ int launch_check_csr(const int64_t* row_ptr, const int32_t* col, int64_t rows, i
                      int64_t n_cols, int32_t* d_flag, hipStream_t s);
 int launch_block_nnz(const int32_t* col, int64_t nnz, int64_t K, int32_t P, int64_t* out,
                      hipStream_t s);
-int run_select(shiro_plan plan, hipStream_t s);
+// Selection kernels; with sync the sizes are read back and the plan marked
+// selected, without it only the device arrays are rewritten.
+int run_select(shiro_plan plan, hipStream_t s, bool sync);
 
 // ---- sort.hip ---------------------------------------------------------------
 // Stable LSD radix sort of (key, value) uint32 pairs on the low `key_bits`
@@ -154,6 +160,7 @@ int ensure_rows_work(shiro_plan plan, int32_t chunk, bool allocate, hipStream_t 
 int ensure_cols_work(shiro_plan plan, int32_t chunk, bool allocate, hipStream_t s,
                      const WorkList** out);
 int ensure_carry(shiro_plan plan, int64_t elems, bool allocate);
+int ensure_acc32(shiro_plan plan, int64_t elems, bool allocate);
 
 shiro_tuning_t default_tuning(int kernel, int32_t N, shiro_dtype dt);
 int validate_tuning(int kernel, int32_t N, shiro_dtype dt, const shiro_tuning_t& t);

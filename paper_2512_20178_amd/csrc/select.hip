@@ -194,7 +194,7 @@ int launch_block_nnz(const int32_t* col, int64_t nnz, int64_t K, int32_t P, int6
   return SHIRO_OK;
 }
 
-int run_select(shiro_plan plan, hipStream_t s) {
+int run_select(shiro_plan plan, hipStream_t s, bool sync) {
   const int64_t nw = plan->n_words;
   const int64_t nnz = plan->nnz;
   // scratch: [U (int64)] [scan tile sums]
@@ -219,6 +219,7 @@ int run_select(shiro_plan plan, hipStream_t s) {
   k_block_off<<<grid_for(plan->P + 1), kBlock, 0, s>>>(plan->bitmap, plan->word_off, plan->n_cols,
                                                         plan->K, plan->P, d_U, plan->block_off);
   SHIRO_LAUNCH_CHECK();
+  if (!sync) return SHIRO_OK;
   SHIRO_HIP(hipMemcpyAsync(plan->h_pinned, plan->block_off, (size_t)(plan->P + 1) * 8,
                            hipMemcpyDeviceToHost, s));
   SHIRO_HIP(hipStreamSynchronize(s));

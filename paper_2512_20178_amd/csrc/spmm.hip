@@ -375,6 +375,16 @@ __global__ void k_zero_rows(T* __restrict__ Y, int64_t rows, int64_t ldy, int32_
   }
 }
 
+__global__ void k_round_rows(const float* __restrict__ src, int64_t lds, bf16_t* __restrict__ dst,
+                             int64_t ldd, int64_t rows, int32_t N) {
+  const int64_t total = rows * (int64_t)N;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / N, c = i - r * N;
+    dst[r * ldd + c] = f32_to_bf16(src[r * lds + c]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // setup kernels: transposed pattern and per-block segments
 // ---------------------------------------------------------------------------
@@ -852,22 +862,31 @@ int launch_spmm_per_block(shiro_plan plan, const float* vals, const void* X, int
       return set_error(SHIRO_ERR_CAPTURING, "per-block spmm: segments not prepared before capture");
     SHIRO_TRY(build_segments(plan, s));
   }
+  if (in_dt == SHIRO_F32 && out_dt != SHIRO_F32)
+    return set_error(SHIRO_ERR_UNSUPPORTED, "spmm: dtype pair not supported");
   const float* v = vals + plan->nz_begin;
   const auto& off = plan->seg.h_off;
-  auto run = [&](auto tin, auto tout, auto L, auto V) -> int {
+  // Block partials are summed in float32: straight into Y when Y is float32,
+  // else into a float32 workspace rounded to bfloat16 once at the end.
+  float* acc = reinterpret_cast<float*>(Y);
+  int64_t lda = ldy;
+  if (out_dt == SHIRO_BF16) {
+    SHIRO_TRY(ensure_acc32(plan, plan->rows * (int64_t)N, !stream_capturing(s)));
+    acc = plan->acc32;
+    lda = N;
+  }
+  auto run = [&](auto tin, auto L, auto V) -> int {
     using TIN = decltype(tin);
-    using TOUT = decltype(tout);
-    k_zero_rows<TOUT><<<grid_for(plan->rows * (int64_t)N, 65536), kBlock, 0, s>>>(
-        (TOUT*)Y, plan->rows, ldy, N);
+    k_zero_rows<float><<<grid_for(plan->rows * (int64_t)N, 65536), kBlock, 0, s>>>(acc, plan->rows, lda, N);
     SHIRO_LAUNCH_CHECK();
     for (int32_t q = 0; q < plan->P; ++q) {
       const int64_t s0 = off[q], s1 = off[q + 1];
       if (s1 <= s0) continue;
       constexpr int G = kWave / decltype(L)::value;
       const unsigned nb = grid_for(ceil_div(s1 - s0, G) * kWave, (int64_t)plan->num_cus * 16);
-      k_spmm_segments<TIN, TOUT, decltype(L)::value, decltype(V)::value><<<nb, kBlock, 0, s>>>(
+      k_spmm_segments<TIN, float, decltype(L)::value, decltype(V)::value><<<nb, kBlock, 0, s>>>(
           plan->seg.seg_row, plan->seg.seg_begin, plan->seg.seg_end, s0, s1, plan->colmap, v,
-          (const TIN*)X, ldx, (TOUT*)Y, ldy, N, 0);
+          (const TIN*)X, ldx, acc, lda, N, 0);
       SHIRO_LAUNCH_CHECK();
     }
     return SHIRO_OK;
@@ -877,19 +896,19 @@ int launch_spmm_per_block(shiro_plan plan, const float* vals, const void* X, int
   using I1 = std::integral_constant<int, 1>;
   using L32 = std::integral_constant<int, 32>;
   using L64 = std::integral_constant<int, 64>;
-  if (in_dt == SHIRO_F32 && out_dt == SHIRO_F32) {
-    if (vec_for<float>(N, {{X, ldx}, {Y, ldy}}) == 4) return run(float{}, float{}, L32{}, I4{});
-    return run(float{}, float{}, L64{}, I1{});
+  if (in_dt == SHIRO_F32) {
+    if (vec_for<float>(N, {{X, ldx}, {acc, lda}}) == 4) SHIRO_TRY(run(float{}, L32{}, I4{}));
+    else SHIRO_TRY(run(float{}, L64{}, I1{}));
+  } else {
+    if (vec_for<bf16_t>(N, {{X, ldx}}) == 8 && aligned16<float>(acc, lda)) SHIRO_TRY(run(bf16_t{}, L32{}, I8{}));
+    else SHIRO_TRY(run(bf16_t{}, L64{}, I1{}));
   }
-  if (in_dt == SHIRO_BF16 && out_dt == SHIRO_F32) {
-    if (vec_for<bf16_t>(N, {{X, ldx}}) == 8 && aligned16<float>(Y, ldy)) return run(bf16_t{}, float{}, L32{}, I8{});
-    return run(bf16_t{}, float{}, L64{}, I1{});
+  if (out_dt == SHIRO_BF16) {
+    k_round_rows<<<grid_for(plan->rows * (int64_t)N, 65536), kBlock, 0, s>>>(acc, lda, (bf16_t*)Y, ldy,
+                                                                             plan->rows, N);
+    SHIRO_LAUNCH_CHECK();
   }
-  if (in_dt == SHIRO_BF16 && out_dt == SHIRO_BF16) {
-    if (vec_for<bf16_t>(N, {{X, ldx}, {Y, ldy}}) == 8) return run(bf16_t{}, bf16_t{}, L32{}, I8{});
-    return run(bf16_t{}, bf16_t{}, L64{}, I1{});
-  }
-  return set_error(SHIRO_ERR_UNSUPPORTED, "spmm: dtype pair not supported");
+  return SHIRO_OK;
 }
 
 int launch_fill_random(float* p, int64_t n, uint64_t seed, hipStream_t s) {
