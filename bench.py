@@ -84,6 +84,8 @@ def main():
     import numpy as np
     import torch
 
+    # the committed tuning table (autotuner results on MI355X) unless overridden
+    os.environ.setdefault("SHIRO_TUNE_CACHE", os.path.join(ROOT, "paper_2512_20178_amd", "tuning_mi355x.txt"))
     import paper_2512_20178_amd as shiro
     import synth
 

@@ -45,6 +45,10 @@ __global__ void k_merge_path(const int64_t* __restrict__ ptr, int32_t R, int64_t
 // ---------------------------------------------------------------------------
 // SpMM: out[r, :] = sum_{k in row r} vals[perm ? perm[k] : k] * X[idx[k], :]
 // ---------------------------------------------------------------------------
+// Host-side bundle of the kernel arguments.  The kernels take them as
+// separate __restrict__ parameters: that tells the compiler the pattern
+// arrays are never written, so wave-uniform reads of them (row pointers,
+// chunk bounds) become scalar loads.
 struct SpmmArgs {
   const int64_t* ptr;       // R + 1
   const int32_t* idx;       // nnz: row of X to gather
@@ -65,15 +69,27 @@ struct SpmmArgs {
   int32_t xcd_remap;
 };
 
+#define SHIRO_SPMM_PARAMS(TIN, TOUT)                                                          \
+  const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,                           \
+      const int32_t *__restrict__ perm, const float *__restrict__ vals,                       \
+      const TIN *__restrict__ X, int64_t ldx, TOUT *__restrict__ out, int64_t ldo,           \
+      TOUT *__restrict__ scat, int64_t lds, const int32_t *__restrict__ scat_idx,             \
+      const int32_t *__restrict__ chunk_row, const int32_t *__restrict__ chunk_nz,            \
+      float *__restrict__ carry, int32_t W, int32_t R, int32_t N, int32_t cpw, int32_t xcd_remap
+
+#define SHIRO_SPMM_ARGS(TIN, TOUT, a)                                                          \
+  (a).ptr, (a).idx, (a).perm, (a).vals, reinterpret_cast<const TIN*>((a).X), (a).ldx,          \
+      reinterpret_cast<TOUT*>((a).out), (a).ldo, reinterpret_cast<TOUT*>((a).scat), (a).lds,   \
+      (a).scat_idx, (a).chunk_row, (a).chunk_nz, (a).carry, (a).W, (a).R, (a).N,               \
+      (a).chunks_per_wave, (a).xcd_remap
+
 template <typename TOUT, int VEC>
-__device__ __forceinline__ void epilogue_row(const SpmmArgs& a, int32_t r, int64_t c,
-                                             const float (&acc)[VEC]) {
-  if (a.out) {
-    TOUT* o = reinterpret_cast<TOUT*>(a.out) + (int64_t)r * a.ldo + c;
-    Elem<TOUT>::template store<VEC>(o, acc);
-  }
-  if (a.scat) {
-    TOUT* o = reinterpret_cast<TOUT*>(a.scat) + (int64_t)a.scat_idx[r] * a.lds + c;
+__device__ __forceinline__ void epilogue_row(TOUT* __restrict__ out, int64_t ldo, TOUT* __restrict__ scat,
+                                             int64_t lds, const int32_t* __restrict__ scat_idx,
+                                             int32_t r, int64_t c, const float (&acc)[VEC]) {
+  if (out) Elem<TOUT>::template store<VEC>(out + (int64_t)r * ldo + c, acc);
+  if (scat) {
+    TOUT* o = scat + (int64_t)scat_idx[r] * lds + c;
     float cur[VEC];
     Elem<TOUT>::template load<VEC>(o, cur);
 #pragma unroll
@@ -91,60 +107,59 @@ __device__ __forceinline__ int32_t logical_block(int32_t remap) {
   return (b & 7) * (g >> 3) + (b >> 3);
 }
 
-template <typename TIN, typename TOUT, int LANES, int VEC, int UNROLL>
-__global__ __launch_bounds__(kBlock) void k_spmm(SpmmArgs a) {
+template <typename TIN, typename TOUT, int LANES, int VEC, int UNROLL, bool PERM>
+__global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
   constexpr int G = kWave / LANES;
+  constexpr int STEP = G * UNROLL;
   const int lane = lane_id();
   const int g = lane / LANES;
   const int li = lane % LANES;
   const int64_t c = (int64_t)blockIdx.y * (LANES * VEC) + (int64_t)li * VEC;
-  const bool cvalid = c < a.N;
-  const TIN* __restrict__ X = reinterpret_cast<const TIN*>(a.X);
-  const int64_t* __restrict__ ptr = a.ptr;
-  const int32_t* __restrict__ idx = a.idx;
-  const int32_t* __restrict__ perm = a.perm;
-  const float* __restrict__ vals = a.vals;
+  const bool cvalid = c < N;
+  const int64_t cl = cvalid ? c : 0;  // idle lanes read an in-bounds column
 
-  const int32_t gw = uniform(logical_block(a.xcd_remap) * kWavesPerBlock + wave_id());
-  const int32_t w_begin = gw * a.chunks_per_wave;
-  int32_t w_end = w_begin + a.chunks_per_wave;
-  if (w_end > a.W) w_end = a.W;
+  const int32_t gw = uniform(logical_block(xcd_remap) * kWavesPerBlock + wave_id());
+  const int32_t w_begin = gw * cpw;
+  const int32_t w_end = min(w_begin + cpw, W);
 
   for (int32_t w = w_begin; w < w_end; ++w) {
-    const int32_t i0 = a.chunk_row[w], i1 = a.chunk_row[w + 1];
-    const int64_t j0 = a.chunk_nz[w], j1 = a.chunk_nz[w + 1];
-    for (int32_t r = i0; r <= i1 && r < a.R; ++r) {
-      const int64_t rs = ptr[r], re = ptr[r + 1];
+    const int32_t i0 = chunk_row[w], i1 = chunk_row[w + 1];
+    const int64_t j0 = chunk_nz[w], j1 = chunk_nz[w + 1];
+    int64_t rs = i0 < R ? ptr[i0] : 0;
+    for (int32_t r = i0; r <= i1 && r < R; ++r) {
+      const int64_t re = ptr[r + 1];
       if (r == i1 && j1 <= rs) break;  // chunk holds nothing of row i1
       const int64_t kb = rs > j0 ? rs : j0;
       const int64_t ke = re < j1 ? re : j1;
       float acc[VEC];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
-      for (int64_t k = kb; k < ke; k += G * UNROLL) {
+      for (int64_t k = kb; k < ke; k += STEP) {
+        // Every slot loads (idle slots re-read the row's last nonzero, a
+        // cache hit) so the loads of all slots are in flight together; the
+        // accumulation of idle slots is masked by a select.
         int32_t xi[UNROLL];
         float v[UNROLL];
+        bool ok[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
           const int64_t kk = k + u * G + g;
-          const bool ok = kk < ke;
-          xi[u] = ok ? idx[kk] : -1;
-          v[u] = ok ? vals[perm ? perm[kk] : kk] : 0.f;
+          ok[u] = kk < ke;
+          const int64_t kc = ok[u] ? kk : ke - 1;
+          xi[u] = idx[kc];
+          v[u] = vals[PERM ? perm[kc] : kc];
         }
         float x[UNROLL][VEC];
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-          if (xi[u] >= 0 && cvalid) {
-            Elem<TIN>::template load<VEC>(X + (int64_t)xi[u] * a.ldx + c, x[u]);
-          } else {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) x[u][e] = 0.f;
-          }
-        }
+        for (int u = 0; u < UNROLL; ++u)
+          Elem<TIN>::template load<VEC>(X + (int64_t)xi[u] * ldx + cl, x[u]);
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) acc[e] = fmaf(v[u], x[u][e], acc[e]);
+          for (int e = 0; e < VEC; ++e) {
+            const float t = fmaf(v[u], x[u][e], acc[e]);
+            acc[e] = ok[u] ? t : acc[e];
+          }
       }
       // combine the lane groups (fixed butterfly order)
 #pragma unroll
@@ -155,40 +170,41 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SpmmArgs a) {
       const bool tail = (r == i1);
       if (g == 0 && cvalid) {
         if (!head && !tail) {
-          epilogue_row<TOUT, VEC>(a, r, c, acc);
+          epilogue_row<TOUT, VEC>(out, ldo, scat, lds, scat_idx, r, c, acc);
         } else {
-          float* cs = a.carry + ((int64_t)w * 2 + (head ? 0 : 1)) * a.N + c;
+          float* cs = carry + ((int64_t)w * 2 + (head ? 0 : 1)) * N + c;
           Elem<float>::template store<VEC>(cs, acc);
         }
       }
+      rs = re;
     }
   }
 }
 
 // Rows split over chunks: sum the tail slot of the starting chunk and the
 // head slots of the following chunks, in chunk order, then the epilogue.
-template <typename TOUT, int VEC>
-__global__ __launch_bounds__(kBlock) void k_fixup(SpmmArgs a) {
+template <typename TIN, typename TOUT, int VEC>
+__global__ __launch_bounds__(kBlock) void k_fixup(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
   const int lane = lane_id();
   const int32_t nwaves = gridDim.x * kWavesPerBlock;
-  for (int32_t w = uniform((int32_t)blockIdx.x * kWavesPerBlock + wave_id()); w < a.W; w += nwaves) {
-    const int32_t r = a.chunk_row[w + 1];
-    if (r >= a.R) continue;
-    const int64_t rs = a.ptr[r];
-    const int64_t j0 = a.chunk_nz[w], j1 = a.chunk_nz[w + 1];
+  for (int32_t w = uniform((int32_t)blockIdx.x * kWavesPerBlock + wave_id()); w < W; w += nwaves) {
+    const int32_t r = chunk_row[w + 1];
+    if (r >= R) continue;
+    const int64_t rs = ptr[r];
+    const int64_t j0 = chunk_nz[w], j1 = chunk_nz[w + 1];
     // chunk w starts row r (no earlier part) and does not finish it
     if (!(j1 > rs && rs >= j0)) continue;
-    for (int64_t c = (int64_t)lane * VEC; c < a.N; c += (int64_t)kWave * VEC) {
+    for (int64_t c = (int64_t)lane * VEC; c < N; c += (int64_t)kWave * VEC) {
       float acc[VEC];
-      Elem<float>::template load<VEC>(a.carry + ((int64_t)w * 2 + 1) * a.N + c, acc);
+      Elem<float>::template load<VEC>(carry + ((int64_t)w * 2 + 1) * N + c, acc);
       for (int32_t w2 = w + 1;; ++w2) {
         float p[VEC];
-        Elem<float>::template load<VEC>(a.carry + ((int64_t)w2 * 2) * a.N + c, p);
+        Elem<float>::template load<VEC>(carry + ((int64_t)w2 * 2) * N + c, p);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) acc[e] += p[e];
-        if (a.chunk_row[w2 + 1] > r) break;
+        if (chunk_row[w2 + 1] > r) break;
       }
-      epilogue_row<TOUT, VEC>(a, r, c, acc);
+      epilogue_row<TOUT, VEC>(out, ldo, scat, lds, scat_idx, r, c, acc);
     }
   }
 }
@@ -212,72 +228,70 @@ struct SddmmArgs {
 };
 
 template <typename TIN, int LANES, int VEC, int UNROLL>
-__global__ __launch_bounds__(kBlock) void k_sddmm(SddmmArgs a) {
+__global__ __launch_bounds__(kBlock) void k_sddmm(
+    const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx, const TIN* __restrict__ dY,
+    int64_t lddy, const TIN* __restrict__ Bp, int64_t ldp, float* __restrict__ dvals,
+    const int32_t* __restrict__ chunk_row, const int32_t* __restrict__ chunk_nz, int32_t W, int32_t R,
+    int32_t N, int32_t cpw, int32_t xcd_remap) {
   constexpr int G = kWave / LANES;
   constexpr int TW = LANES * VEC;
+  constexpr int STEP = G * UNROLL;
   const int lane = lane_id();
   const int g = lane / LANES;
   const int li = lane % LANES;
-  const TIN* __restrict__ dY = reinterpret_cast<const TIN*>(a.dY);
-  const TIN* __restrict__ Bp = reinterpret_cast<const TIN*>(a.Bp);
-  const int64_t* __restrict__ ptr = a.ptr;
-  const int32_t* __restrict__ idx = a.idx;
-  const int ntiles = (a.N + TW - 1) / TW;
+  const int ntiles = (N + TW - 1) / TW;
+  const int64_t c0 = (int64_t)li * VEC;
 
-  const int32_t gw = uniform(logical_block(a.xcd_remap) * kWavesPerBlock + wave_id());
-  const int32_t w_begin = gw * a.chunks_per_wave;
-  int32_t w_end = w_begin + a.chunks_per_wave;
-  if (w_end > a.W) w_end = a.W;
+  const int32_t gw = uniform(logical_block(xcd_remap) * kWavesPerBlock + wave_id());
+  const int32_t w_begin = gw * cpw;
+  const int32_t w_end = min(w_begin + cpw, W);
 
   for (int32_t w = w_begin; w < w_end; ++w) {
-    const int32_t i0 = a.chunk_row[w], i1 = a.chunk_row[w + 1];
-    const int64_t j0 = a.chunk_nz[w], j1 = a.chunk_nz[w + 1];
-    for (int32_t r = i0; r <= i1 && r < a.R; ++r) {
-      const int64_t rs = ptr[r], re = ptr[r + 1];
+    const int32_t i0 = chunk_row[w], i1 = chunk_row[w + 1];
+    const int64_t j0 = chunk_nz[w], j1 = chunk_nz[w + 1];
+    int64_t rs = i0 < R ? ptr[i0] : 0;
+    for (int32_t r = i0; r <= i1 && r < R; ++r) {
+      const int64_t re = ptr[r + 1];
       const int64_t kb = rs > j0 ? rs : j0;
       const int64_t ke = re < j1 ? re : j1;
+      rs = re;
       if (kb >= ke) continue;
       // first column tile of dY row r stays in registers for the whole row
-      const int64_t c0 = (int64_t)li * VEC;
       float y0[VEC];
-      if (c0 < a.N) {
-        Elem<TIN>::template load<VEC>(dY + (int64_t)r * a.lddy + c0, y0);
-      } else {
+      Elem<TIN>::template load<VEC>(dY + (int64_t)r * lddy + (c0 < N ? c0 : 0), y0);
+      if (c0 >= N) {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) y0[e] = 0.f;
       }
-      for (int64_t k = kb; k < ke; k += G * UNROLL) {
+      for (int64_t k = kb; k < ke; k += STEP) {
         int32_t xi[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
           const int64_t kk = k + u * G + g;
-          xi[u] = kk < ke ? idx[kk] : -1;
+          xi[u] = idx[kk < ke ? kk : ke - 1];
         }
         float part[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
+          float b[VEC];
+          Elem<TIN>::template load<VEC>(Bp + (int64_t)xi[u] * ldp + (c0 < N ? c0 : 0), b);
           part[u] = 0.f;
-          if (xi[u] >= 0 && c0 < a.N) {
-            float b[VEC];
-            Elem<TIN>::template load<VEC>(Bp + (int64_t)xi[u] * a.ldp + c0, b);
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) part[u] = fmaf(y0[e], b[e], part[u]);
-          }
+          for (int e = 0; e < VEC; ++e) part[u] = fmaf(y0[e], b[e], part[u]);
         }
         for (int t = 1; t < ntiles; ++t) {
           const int64_t ct = (int64_t)t * TW + c0;
-          if (ct < a.N) {
-            float y[VEC];
-            Elem<TIN>::template load<VEC>(dY + (int64_t)r * a.lddy + ct, y);
+          const bool cv = ct < N;
+          float y[VEC];
+          Elem<TIN>::template load<VEC>(dY + (int64_t)r * lddy + (cv ? ct : 0), y);
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
-              if (xi[u] >= 0) {
-                float b[VEC];
-                Elem<TIN>::template load<VEC>(Bp + (int64_t)xi[u] * a.ldp + ct, b);
+          for (int u = 0; u < UNROLL; ++u) {
+            float b[VEC];
+            Elem<TIN>::template load<VEC>(Bp + (int64_t)xi[u] * ldp + (cv ? ct : 0), b);
+            float q = 0.f;
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) part[u] = fmaf(y[e], b[e], part[u]);
-              }
-            }
+            for (int e = 0; e < VEC; ++e) q = fmaf(y[e], b[e], q);
+            part[u] += cv ? q : 0.f;
           }
         }
 #pragma unroll
@@ -285,7 +299,7 @@ __global__ __launch_bounds__(kBlock) void k_sddmm(SddmmArgs a) {
 #pragma unroll
           for (int sft = 1; sft < LANES; sft <<= 1) part[u] += __shfl_xor(part[u], sft, kWave);
           const int64_t kk = k + u * G + g;
-          if (li == 0 && kk < ke) a.dvals[kk] = part[u];
+          if (li == 0 && kk < ke) dvals[kk] = part[u];
         }
       }
     }
@@ -519,13 +533,13 @@ int grid_waves(shiro_plan plan, const shiro_tuning_t& t, int32_t W, int32_t* chu
   return SHIRO_OK;
 }
 
-template <typename TIN, typename TOUT, int VEC>
+template <typename TIN, typename TOUT, int VEC, bool PERM>
 int spmm_dispatch(const shiro_tuning_t& t, dim3 grid, hipStream_t s, const SpmmArgs& a) {
-#define SHIRO_SPMM_CASE(L, U)                                                  \
-  if (t.lanes == L && t.unroll == U) {                                         \
-    k_spmm<TIN, TOUT, L, VEC, U><<<grid, kBlock, 0, s>>>(a);                   \
-    SHIRO_LAUNCH_CHECK();                                                      \
-    return SHIRO_OK;                                                           \
+#define SHIRO_SPMM_CASE(L, U)                                                               \
+  if (t.lanes == L && t.unroll == U) {                                                      \
+    k_spmm<TIN, TOUT, L, VEC, U, PERM><<<grid, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a)); \
+    SHIRO_LAUNCH_CHECK();                                                                   \
+    return SHIRO_OK;                                                                        \
   }
   SHIRO_SPMM_CASE(8, 1) SHIRO_SPMM_CASE(8, 2) SHIRO_SPMM_CASE(8, 4)
   SHIRO_SPMM_CASE(16, 1) SHIRO_SPMM_CASE(16, 2) SHIRO_SPMM_CASE(16, 4)
@@ -537,11 +551,14 @@ int spmm_dispatch(const shiro_tuning_t& t, dim3 grid, hipStream_t s, const SpmmA
 
 template <typename TIN, int VEC>
 int sddmm_dispatch(const shiro_tuning_t& t, dim3 grid, hipStream_t s, const SddmmArgs& a) {
-#define SHIRO_SDDMM_CASE(L, U)                                                 \
-  if (t.lanes == L && t.unroll == U) {                                         \
-    k_sddmm<TIN, L, VEC, U><<<grid, kBlock, 0, s>>>(a);                        \
-    SHIRO_LAUNCH_CHECK();                                                      \
-    return SHIRO_OK;                                                           \
+#define SHIRO_SDDMM_CASE(L, U)                                                              \
+  if (t.lanes == L && t.unroll == U) {                                                      \
+    k_sddmm<TIN, L, VEC, U><<<grid, kBlock, 0, s>>>(                                        \
+        a.ptr, a.idx, reinterpret_cast<const TIN*>(a.dY), a.lddy,                           \
+        reinterpret_cast<const TIN*>(a.Bp), a.ldp, a.dvals, a.chunk_row, a.chunk_nz, a.W,   \
+        a.R, a.N, a.chunks_per_wave, a.xcd_remap);                                          \
+    SHIRO_LAUNCH_CHECK();                                                                   \
+    return SHIRO_OK;                                                                        \
   }
   SHIRO_SDDMM_CASE(8, 1) SHIRO_SDDMM_CASE(8, 2) SHIRO_SDDMM_CASE(8, 4)
   SHIRO_SDDMM_CASE(16, 1) SHIRO_SDDMM_CASE(16, 2) SHIRO_SDDMM_CASE(16, 4)
@@ -568,16 +585,19 @@ int run_spmm_family(shiro_plan plan, shiro_tuning_t t, const WorkList* wl, SpmmA
   const int ntiles = (int)ceil_div(a.N, (int64_t)t.lanes * vec);
   a.xcd_remap = t.xcd_remap;
   dim3 grid(nb, ntiles);
-  if (vec == Elem<TIN>::kVec16) {
-    SHIRO_TRY((spmm_dispatch<TIN, TOUT, Elem<TIN>::kVec16>(t, grid, s, a)));
+  constexpr int V16 = Elem<TIN>::kVec16;
+  if (a.perm) {
+    if (vec == V16) SHIRO_TRY((spmm_dispatch<TIN, TOUT, V16, true>(t, grid, s, a)));
+    else SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1, true>(t, grid, s, a)));
   } else {
-    SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1>(t, grid, s, a)));
+    if (vec == V16) SHIRO_TRY((spmm_dispatch<TIN, TOUT, V16, false>(t, grid, s, a)));
+    else SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1, false>(t, grid, s, a)));
   }
   const unsigned fb = grid_for((int64_t)wl->W * kWave, 4096);
-  if (vec == Elem<TIN>::kVec16 && (a.N % 4) == 0) {
-    k_fixup<TOUT, 4><<<fb, kBlock, 0, s>>>(a);
+  if (vec == V16 && (a.N % 4) == 0) {
+    k_fixup<TIN, TOUT, 4><<<fb, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a));
   } else {
-    k_fixup<TOUT, 1><<<fb, kBlock, 0, s>>>(a);
+    k_fixup<TIN, TOUT, 1><<<fb, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a));
   }
   SHIRO_LAUNCH_CHECK();
   return SHIRO_OK;

@@ -1,0 +1,282 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+benchmark times (the tuning table it reads), on outputs the oracle can
+compute one by one (sampled rows / packed columns) or on properties that fix
+the result at any size.
+
+Workloads (seed 0):
+  rmat24_p128_panel0  panel 0 of a 2^24 R-MAT at P = 128, N = 128, float32
+  er24_p128_panel0    panel 0 of a 2^24 Erdos-Renyi matrix, N in {32,64,128,256}
+  rmat22_ef64         2^22 R-MAT (~250M nonzeros), N = 256, bfloat16 storage
+  gcn_rmat21_ef25     normalised symmetric 2^21 R-MAT, N = 128, autograd
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TOL_F32 = 1e-5
+TOL_BF16 = 1e-2
+
+
+@pytest.fixture(scope="module")
+def shiro():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2512_20178_amd as s
+
+    s._lib.load()
+    os.environ.setdefault("SHIRO_TUNE_CACHE", os.path.join(ROOT, "paper_2512_20178_amd", "tuning_mi355x.txt"))
+    return s
+
+
+def host_csr(A):
+    return oracle.Csr(A.n_rows, A.n_cols, A.row_ptr.cpu().numpy(), A.col.cpu().numpy(), A.vals.cpu().numpy(),
+                      A.P, A.p)
+
+
+def sample_rows(Ac, n=160, seed=0):
+    """Evenly spaced rows, the longest rows and some empty rows of the panel."""
+    rp = Ac.row_ptr[Ac.row_begin:Ac.row_end + 1]
+    lens = np.diff(rp)
+    rng = np.random.default_rng(seed)
+    pick = [np.linspace(0, Ac.M - 1, n // 2).astype(np.int64), np.argsort(lens)[-8:]]
+    empty = np.nonzero(lens == 0)[0]
+    if empty.size:
+        pick.append(rng.choice(empty, min(8, empty.size), replace=False))
+    pick.append(rng.integers(0, Ac.M, n // 2))
+    return np.unique(np.concatenate(pick))
+
+
+def check_selection_properties(shiro, plan, A):
+    """unique_cols strictly ascending inside blocks and within each block's
+    column range, every packed position used, and unique_cols[colmap] == col:
+    together these fix the selection uniquely (the sorted set Cols of each block)."""
+    uc, off, cm = shiro.selection(plan)
+    inf = plan.info()
+    col = A.col[inf["nz_begin"]:inf["nz_begin"] + inf["nnz"]]
+    assert torch.equal(uc[cm.long()], col)
+    assert torch.equal(torch.bincount(cm.long(), minlength=uc.numel()) > 0, torch.ones(uc.numel(), dtype=torch.bool, device=uc.device))
+    offh = off.cpu().numpy()
+    K = inf["K"]
+    blk = torch.div(uc.long(), K, rounding_mode="floor")
+    assert torch.all(blk[1:] >= blk[:-1])
+    starts = torch.searchsorted(blk, torch.arange(inf["P"] + 1, device=uc.device))
+    assert np.array_equal(starts.cpu().numpy(), offh)
+    d = uc[1:].long() - uc[:-1].long()
+    assert torch.all(d > 0)
+
+
+# ----------------------------------------------------------------------------
+# panel 0 of the 2^24 R-MAT at P = 128 (the benchmark's workload)
+# ----------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def rmat24(shiro):
+    dev = torch.device("cuda")
+    A = synth.config2(device=dev)
+    N = 128
+    B = synth.dense(A.n_cols, N, 0, synth.STREAM_B, device=dev)
+    plan = shiro.partition(A.row_ptr, A.col, A.n_rows, A.n_cols, A.P, A.p, check=True)
+    U, Uq = shiro.select_rows(plan)
+    shiro.autotune(plan, N, torch.float32, ops=("spmm", "backward"))
+    Ac = host_csr(A)
+    return dict(A=A, N=N, B=B, plan=plan, U=U, Uq=Uq, Ac=Ac)
+
+
+def test_rmat24_select_bit_exact(shiro, rmat24):
+    uc, off, cm = oracle.select(rmat24["Ac"])
+    guc, goff, gcm = (t.cpu().numpy() for t in shiro.selection(rmat24["plan"]))
+    assert np.array_equal(guc, uc) and np.array_equal(goff, off) and np.array_equal(gcm, cm)
+    assert rmat24["Uq"] == list(np.diff(off))
+    assert np.array_equal(shiro.block_nnz(rmat24["plan"]).cpu().numpy(), oracle.block_nnz(rmat24["Ac"]))
+
+
+def test_rmat24_pack_bit_exact(shiro, rmat24):
+    plan, B = rmat24["plan"], rmat24["B"]
+    Bp = shiro.pack_B(plan, B)
+    uc = torch.from_numpy(oracle.select(rmat24["Ac"])[0]).to(B.device)
+    assert torch.equal(Bp, B.index_select(0, uc.long()))
+
+
+def test_rmat24_spmm_and_backward_sampled(shiro, rmat24):
+    plan, B, N, Ac, A = rmat24["plan"], rmat24["B"], rmat24["N"], rmat24["Ac"], rmat24["A"]
+    dev = B.device
+    Bp = shiro.pack_B(plan, B)
+    Y = shiro.spmm(plan, A.vals, Bp)
+    Y2 = shiro.spmm(plan, A.vals, Bp)
+    assert torch.equal(Y, Y2)
+    rows = sample_rows(Ac)
+    Bh = B.cpu().numpy()
+    yref = oracle.spmm_rows(Ac, rows, Bh, None)
+    den = oracle.spmm_rows(Ac, rows, Bh, None, abs_mode=True)
+    assert oracle.rel_err(Y[torch.from_numpy(rows).to(dev)].cpu().numpy(), yref, den) <= TOL_F32
+    # per-block mode (one launch per column block) on the same rows
+    Ypb = shiro.spmm(plan, A.vals, Bp, mode="per_block")
+    assert oracle.rel_err(Ypb[torch.from_numpy(rows).to(dev)].cpu().numpy(), yref, den) <= TOL_F32
+    # backward: sampled packed columns of A^T dY and all dvals
+    G = synth.dense(Ac.M, N, 0, synth.STREAM_DY, device=dev)
+    dBp = torch.empty(rmat24["U"], N, device=dev)
+    dvals = torch.zeros(A.nnz, device=dev)
+    shiro.spmm_backward(plan, A.vals, G, Bp, dBpacked=dBp, dvals=dvals)
+    uc, off, cm = oracle.select(Ac)
+    rng = np.random.default_rng(1)
+    tgt = np.unique(np.concatenate([rng.integers(0, len(uc), 200), np.arange(0, 16), off[1:-1][:32]]))
+    Gh = G.cpu().numpy()
+    ref = oracle.spmm_t_sampled(Ac, Gh, cm, len(uc), tgt)
+    rden = oracle.spmm_t_sampled(Ac, Gh, cm, len(uc), tgt, abs_mode=True)
+    assert oracle.rel_err(dBp[torch.from_numpy(tgt).to(dev)].cpu().numpy(), ref, rden) <= TOL_F32
+    Bph = oracle.pack(Bh, uc)
+    dv = oracle.sddmm(Ac, Gh, Bph, cm)
+    dvden = oracle.sddmm(Ac, Gh, Bph, cm, abs_mode=True)
+    assert oracle.rel_err(dvals.cpu().numpy()[Ac.nz_begin:Ac.nz_begin + Ac.nnz_panel], dv, dvden) <= TOL_F32
+
+
+# ----------------------------------------------------------------------------
+# Erdos-Renyi panel, every dense width of the N sweep
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("N", [32, 64, 128, 256])
+def test_er24_n_sweep(shiro, N):
+    dev = torch.device("cuda")
+    A = synth.config3_er(device=dev)
+    plan = shiro.partition(A.row_ptr, A.col, A.n_rows, A.n_cols, A.P, A.p)
+    U, _ = shiro.select_rows(plan)
+    check_selection_properties(shiro, plan, A)
+    shiro.autotune(plan, N, torch.float32, ops=("spmm",))
+    B = synth.dense(A.n_cols, N, 0, synth.STREAM_B, device=dev)
+    Bp = shiro.pack_B(plan, B)
+    Y = shiro.spmm(plan, A.vals, Bp)
+    Ypb = shiro.spmm(plan, A.vals, Bp, mode="per_block")
+    Ac = host_csr(A)
+    rows = sample_rows(Ac, 96)
+    idx = torch.from_numpy(rows).to(dev)
+    Bh = B.cpu().numpy()
+    yref = oracle.spmm_rows(Ac, rows, Bh, None)
+    den = oracle.spmm_rows(Ac, rows, Bh, None, abs_mode=True)
+    assert oracle.rel_err(Y[idx].cpu().numpy(), yref, den) <= TOL_F32
+    assert oracle.rel_err(Ypb[idx].cpu().numpy(), yref, den) <= TOL_F32
+
+
+# ----------------------------------------------------------------------------
+# 2^22 R-MAT, bfloat16 storage, N = 256
+# ----------------------------------------------------------------------------
+def test_rmat22_bf16(shiro):
+    dev = torch.device("cuda")
+    A = synth.config4(device=dev)
+    N = 256
+    plan = shiro.partition(A.row_ptr, A.col, A.n_rows, A.n_cols, A.P, A.p)
+    U, _ = shiro.select_rows(plan)
+    check_selection_properties(shiro, plan, A)
+    B = synth.dense(A.n_cols, N, 0, synth.STREAM_B, device=dev)
+    Bh16 = B.to(torch.bfloat16)
+    shiro.autotune(plan, N, torch.bfloat16, ops=("spmm",))
+    Bp = shiro.pack_B(plan, Bh16)
+    uc, _, _ = shiro.selection(plan)
+    assert torch.equal(Bp.view(torch.int16), Bh16.index_select(0, uc.long()).view(torch.int16))
+    Yf = shiro.spmm(plan, A.vals, Bp, out_dtype=torch.float32)
+    Yh = shiro.spmm(plan, A.vals, Bp, out_dtype=torch.bfloat16)
+    Ac = host_csr(A)
+    rows = sample_rows(Ac, 48)
+    idx = torch.from_numpy(rows).to(dev)
+    # only the referenced rows of B go to the host
+    rp = Ac.row_ptr
+    cols = np.unique(np.concatenate([Ac.col[rp[r]:rp[r + 1]] for r in rows]))
+    remap = np.zeros(A.n_cols, np.int32)
+    remap[cols] = np.arange(cols.size, dtype=np.int32)
+    sub = oracle.Csr(A.n_rows, cols.size, rp, remap[Ac.col], Ac.vals, 1, 0)
+    Bf = B.index_select(0, torch.from_numpy(cols).to(dev).long()).cpu().numpy()
+    yref = oracle.spmm_rows(sub, rows, Bf, None)  # FP64 on the original float32 B
+    den = oracle.spmm_rows(sub, rows, Bf, None, abs_mode=True)
+    assert oracle.rel_err(Yf[idx].cpu().numpy(), yref, den) <= TOL_BF16
+    assert oracle.rel_err(Yh[idx].float().cpu().numpy(), yref, den) <= TOL_BF16
+    # kernel-only error on the bf16-rounded B
+    Bq = Bh16.index_select(0, torch.from_numpy(cols).to(dev).long()).float().cpu().numpy()
+    yq = oracle.spmm_rows(sub, rows, Bq, None)
+    dq = oracle.spmm_rows(sub, rows, Bq, None, abs_mode=True)
+    assert oracle.rel_err(Yf[idx].cpu().numpy(), yq, dq) <= TOL_F32
+
+
+# ----------------------------------------------------------------------------
+# GCN layer: autograd end to end, FP64 finite differences on a subgraph
+# ----------------------------------------------------------------------------
+def test_gcn_autograd_full_size(shiro):
+    dev = torch.device("cuda")
+    A = synth.config5(device=dev)
+    N = 128
+    plan = shiro.partition(A.row_ptr, A.col, A.n_rows, A.n_cols, 1, 0)
+    U, _ = shiro.select_rows(plan)
+    shiro.autotune(plan, N, torch.float32, ops=("spmm", "backward"))
+    B = synth.dense(A.n_cols, N, 0, synth.STREAM_B, device=dev).requires_grad_(True)
+    vals = A.vals.clone().requires_grad_(True)
+    G = synth.dense(A.n_rows, N, 0, synth.STREAM_DY, device=dev)
+    Y = shiro.shiro_spmm(plan, vals, B)
+    Y.backward(G)
+    Ac = host_csr(A)
+    rows = sample_rows(Ac, 64)
+    idx = torch.from_numpy(rows).to(dev)
+    Bh = B.detach().cpu().numpy()
+    yref = oracle.spmm_rows(Ac, rows, Bh, None)
+    den = oracle.spmm_rows(Ac, rows, Bh, None, abs_mode=True)
+    assert oracle.rel_err(Y.detach()[idx].cpu().numpy(), yref, den) <= TOL_F32
+    # A is symmetric here, so A^T dY rows equal A dY rows: check through the
+    # oracle's product with G (transpose is checked on non-symmetric panels
+    # in the other tests)
+    Gh = G.cpu().numpy()
+    gref = oracle.spmm_rows(Ac, rows, Gh, None)
+    gden = oracle.spmm_rows(Ac, rows, Gh, None, abs_mode=True)
+    assert oracle.rel_err(B.grad[idx].cpu().numpy(), gref, gden) <= TOL_F32
+    # dvals at the nonzeros of the sampled rows (a CSR of just those rows)
+    rp = Ac.row_ptr
+    ks = np.concatenate([np.arange(rp[r], rp[r + 1]) for r in rows])
+    gv = vals.grad[torch.from_numpy(ks).to(dev)].cpu().numpy()
+    lens = np.array([rp[r + 1] - rp[r] for r in rows])
+    srp = np.zeros(len(rows) + 1, np.int64)
+    np.cumsum(lens, out=srp[1:])
+    sub = oracle.Csr(len(rows), Ac.n_cols, srp, Ac.col[ks], Ac.vals[ks], 1, 0)
+    dv = oracle.sddmm(sub, Gh[rows], Bh, None)
+    dvden = oracle.sddmm(sub, Gh[rows], Bh, None, abs_mode=True)
+    assert oracle.rel_err(gv, dv, dvden) <= TOL_F32
+
+
+def test_gcn_finite_differences_subgraph(shiro):
+    """Induced subgraph on vertices 0..1023: gradients of L = <G, A B> from the
+    GPU path against FP64 central differences of the oracle's L (exact for any
+    step because L is bilinear)."""
+    dev = torch.device("cuda")
+    A = synth.induced_subgraph(synth.config5(device=dev), 1024)
+    N = 128
+    plan = shiro.partition(A.row_ptr, A.col, A.n_rows, A.n_cols, 1, 0)
+    shiro.select_rows(plan)
+    B = synth.dense(A.n_cols, N, 0, synth.STREAM_B, device=dev)
+    # B on a 2^-10 grid so that B +- E stays exact in float32
+    B = (torch.clamp(B, -7, 7) * 1024).round() / 1024
+    B.requires_grad_(True)
+    vals = A.vals.clone().requires_grad_(True)
+    G = synth.dense(A.n_rows, N, 0, synth.STREAM_DY, device=dev)
+    Y = shiro.shiro_spmm(plan, vals, B)
+    (Y * G).sum().backward()
+    Ac = host_csr(A)
+    Bh, Gh = B.detach().cpu().numpy(), G.cpu().numpy()
+
+    def L(Bm, v=None):
+        Am = Ac if v is None else oracle.Csr(Ac.n_rows, Ac.n_cols, Ac.row_ptr, Ac.col, v, 1, 0)
+        return float(np.sum(Gh.astype(np.float64) * oracle.spmm(Am, Bm, None)))
+
+    rng = np.random.default_rng(7)
+    dB = B.grad.cpu().numpy().astype(np.float64)
+    dvg = vals.grad.cpu().numpy().astype(np.float64)
+    absL = float(np.sum(np.abs(Gh) * oracle.spmm(Ac, Bh, None, abs_mode=True)))
+    for _ in range(4):
+        E = rng.choice([-1.0, 0.0, 1.0], size=Bh.shape).astype(np.float32)
+        fd = (L(Bh + E) - L(Bh - E)) / 2.0
+        assert abs(fd - float(np.sum(dB * E))) <= 1e-5 * absL
+        # values direction: 64 random coordinates, step 0.5 (exact: |v| <= 1)
+        e = np.zeros_like(Ac.vals)
+        e[rng.integers(0, Ac.vals.size, 64)] = 0.5
+        fdv = (L(Bh, Ac.vals + e) - L(Bh, Ac.vals - e)) / (2 * 0.5)
+        assert abs(fdv - float(np.sum(dvg * (e / 0.5)))) <= 1e-5 * absL

@@ -244,3 +244,122 @@ def test_tunings_all_correct(shiro, run, knobs):
     for k in ("spmm", "spmm_t", "sddmm"):  # back to the defaults for other tests
         shiro.set_tuning(run.plan, k, run.N, torch.float32, chunk=256 if k != "sddmm" else 512, lanes=64,
                          unroll=2, xcd_remap=0, wg_per_cu=8)
+
+
+def test_graph_replays_match_eager(shiro):
+    """A captured select+pack+spmm+backward graph, replayed several times with
+    eager work in between, gives bit-identical results to the eager calls."""
+    A, N = make_case("rmat12_P8_p0")
+    dev = torch.device("cuda")
+    Ad = A.to(dev)
+    plan = shiro.partition(Ad.row_ptr, Ad.col, A.n_rows, A.n_cols, A.P, A.p)
+    U, _ = shiro.select_rows(plan)
+    shiro.prepare(plan, N, torch.float32, ops=("spmm", "backward"))
+    B = synth.dense(A.n_cols, N, 0, synth.STREAM_B).to(dev)
+    G = synth.dense(plan.info()["rows"], N, 0, synth.STREAM_DY).to(dev)
+    Bp = torch.empty(U, N, device=dev)
+    Y = torch.empty(plan.info()["rows"], N, device=dev)
+    dBp = torch.empty(U, N, device=dev)
+    dvals = torch.zeros(A.nnz, device=dev)
+
+    def step():
+        shiro.refresh_selection(plan)
+        shiro.pack_B(plan, B, out=Bp)
+        shiro.spmm(plan, Ad.vals, Bp, out=Y)
+        shiro.spmm_backward(plan, Ad.vals, G, Bp, dBpacked=dBp, dvals=dvals)
+
+    step()
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in (Bp, Y, dBp, dvals)]
+    cs = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with plan.capture(cs) as holder:
+        step()
+    gid = holder[0]
+    for i in range(4):
+        for t in (Bp, Y, dBp, dvals):
+            t.fill_(float("nan"))
+        torch.cuda.synchronize()
+        plan.replay(gid, stream=cs)
+        cs.synchronize()
+        for a, b in zip((Bp, Y, dBp, dvals), ref):
+            assert torch.equal(a, b), f"replay {i}"
+        _ = (B * 2).sum().item()  # unrelated eager work between replays
+    uc, off, cm = shiro.selection(plan)
+    Ac = oracle.Csr.from_synth(A)
+    ruc, roff, rcm = oracle.select(Ac)
+    assert np.array_equal(uc.cpu().numpy(), ruc) and np.array_equal(cm.cpu().numpy(), rcm)
+
+
+def test_autograd_function(shiro):
+    A, N = make_case("rmat11_P7_p6_ragged")
+    dev = torch.device("cuda")
+    Ad = A.to(dev)
+    plan = shiro.partition(Ad.row_ptr, Ad.col, A.n_rows, A.n_cols, A.P, A.p)
+    shiro.select_rows(plan)
+    B = synth.dense(A.n_cols, N, 0, synth.STREAM_B).to(dev).requires_grad_(True)
+    vals = Ad.vals.clone().requires_grad_(True)
+    Y = shiro.shiro_spmm(plan, vals, B)
+    G = synth.dense(Y.shape[0], N, 0, synth.STREAM_DY).to(dev)
+    (Y * G).sum().backward()
+    Ac = oracle.Csr.from_synth(A)
+    Gn, Bn = G.cpu().numpy(), B.detach().cpu().numpy()
+    dB = oracle.spmm_t(Ac, Gn, None)
+    den = oracle.spmm_t(Ac, Gn, None, abs_mode=True)
+    assert oracle.rel_err(B.grad.cpu().numpy(), dB, den) <= TOL_F32
+    dv = np.zeros(A.nnz)
+    dvd = np.zeros(A.nnz)
+    dv[Ac.nz_begin:Ac.nz_begin + Ac.nnz_panel] = oracle.sddmm(Ac, Gn, Bn, None)
+    dvd[Ac.nz_begin:Ac.nz_begin + Ac.nnz_panel] = oracle.sddmm(Ac, Gn, Bn, None, abs_mode=True)
+    assert oracle.rel_err(vals.grad.cpu().numpy(), dv, dvd) <= TOL_F32
+
+
+def test_autotune_then_correct(shiro):
+    A, N = make_case("rmat12_P8_p0")
+    dev = torch.device("cuda")
+    Ad = A.to(dev)
+    plan = shiro.partition(Ad.row_ptr, Ad.col, A.n_rows, A.n_cols, A.P, A.p)
+    shiro.select_rows(plan)
+    shiro.autotune(plan, N, torch.float32, ops=("spmm", "backward"))
+    for k in ("spmm", "spmm_t", "sddmm"):
+        t = shiro.get_tuning(plan, k, N)
+        assert t["lanes"] in (8, 16, 32, 64) and t["unroll"] in (1, 2, 4)
+    B = synth.dense(A.n_cols, N, 0, synth.STREAM_B).to(dev)
+    Y = shiro.spmm(plan, Ad.vals, shiro.pack_B(plan, B))
+    Ac = oracle.Csr.from_synth(A)
+    Yref = oracle.spmm(Ac, B.cpu().numpy(), None)
+    den = oracle.spmm(Ac, B.cpu().numpy(), None, abs_mode=True)
+    assert oracle.rel_err(Y.cpu().numpy(), Yref, den) <= TOL_F32
+
+
+def test_error_paths_on_device(shiro):
+    dev = torch.device("cuda")
+    # malformed CSR caught by the check mode
+    rp = torch.tensor([0, 2, 1, 3], dtype=torch.int64, device=dev)
+    col = torch.tensor([0, 1, 2], dtype=torch.int32, device=dev)
+    with pytest.raises(shiro.ShiroError) as e:
+        shiro.partition(rp, col, 3, 3, 1, 0, check=True)
+    assert e.value.name == "BAD_CSR"
+    rp = torch.tensor([0, 2, 3], dtype=torch.int64, device=dev)
+    col = torch.tensor([1, 1, 0], dtype=torch.int32, device=dev)  # repeated column in row 0
+    with pytest.raises(shiro.ShiroError) as e:
+        shiro.partition(rp, col, 2, 3, 1, 0, check=True)
+    assert e.value.name == "BAD_CSR"
+    col = torch.tensor([0, 1, 7], dtype=torch.int32, device=dev)  # column out of range
+    with pytest.raises(shiro.ShiroError) as e:
+        shiro.partition(rp, col, 2, 3, 1, 0, check=True)
+    assert e.value.name == "BAD_CSR"
+    # call order
+    col = torch.tensor([0, 1, 2], dtype=torch.int32, device=dev)
+    plan = shiro.partition(rp, col, 2, 3, 1, 0, check=True)
+    B = torch.zeros(3, 4, device=dev)
+    with pytest.raises(shiro.ShiroError) as e:
+        shiro.pack_B(plan, B, out=torch.zeros(3, 4, device=dev))
+    assert e.value.name == "NOT_READY"
+    shiro.select_rows(plan)
+    with pytest.raises(shiro.ShiroError) as e:  # float32 input with bfloat16 output
+        shiro.spmm(plan, torch.ones(3, device=dev), torch.zeros(3, 4, device=dev), out_dtype=torch.bfloat16)
+    assert e.value.name == "UNSUPPORTED"
+    with pytest.raises(shiro.ShiroError) as e:
+        shiro.set_tuning(plan, "spmm", 4, lanes=12)
+    assert e.value.name == "INVALID_ARG"
