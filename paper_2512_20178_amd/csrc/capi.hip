@@ -109,6 +109,14 @@ int ensure_acc32(shiro_plan plan, int64_t elems, bool allocate) {
   return SHIRO_OK;
 }
 
+int ensure_tvals(shiro_plan plan, bool allocate) {
+  if (plan->tvals_elems >= plan->nnz && plan->tvals) return SHIRO_OK;
+  if (!allocate) return set_error(SHIRO_ERR_CAPTURING, "transposed values buffer not prepared before capture");
+  SHIRO_TRY(dev_alloc_n(&plan->tvals, std::max<int64_t>(plan->nnz, 1)));
+  plan->tvals_elems = plan->nnz;
+  return SHIRO_OK;
+}
+
 shiro_tuning_t default_tuning(int kernel, int32_t, shiro_dtype) {
   shiro_tuning_t t;
   t.chunk = kernel == SHIRO_KERNEL_SDDMM ? 512 : 256;
@@ -154,19 +162,19 @@ static void plan_free(shiro_plan plan) {
     if (g) (void)hipGraphExecDestroy(g);
   dev_free(plan->row_ptr);
   dev_free(plan->col);
+  dev_free(plan->flags);
   dev_free(plan->bitmap);
   dev_free(plan->word_off);
   dev_free(plan->unique_cols);
   dev_free(plan->block_off);
   dev_free(plan->colmap);
-  for (auto& kv : plan->rows_work) {
-    dev_free(kv.second.chunk_row);
-    dev_free(kv.second.chunk_nz);
-  }
-  for (auto& kv : plan->cols_work) {
-    dev_free(kv.second.chunk_row);
-    dev_free(kv.second.chunk_nz);
-  }
+  for (auto* m : {&plan->rows_work, &plan->cols_work})
+    for (auto& kv : *m) {
+      dev_free(kv.second.chunk_row);
+      dev_free(kv.second.chunk_nz);
+      dev_free(kv.second.split);
+    }
+  dev_free(plan->tvals);
   dev_free(plan->tr.ptr);
   dev_free(plan->tr.row);
   dev_free(plan->tr.perm);
@@ -384,6 +392,7 @@ SHIRO_API int shiro_partition(int64_t n_rows, int64_t n_cols, int64_t nnz, const
   int rc;
   if ((rc = dev_alloc_n(&plan->row_ptr, plan->rows + 1)) ||
       (rc = dev_alloc_n(&plan->col, std::max<int64_t>(plan->nnz, 1))) ||
+      (rc = dev_alloc_n(&plan->flags, plan->n_words * 32)) ||
       (rc = dev_alloc_n(&plan->bitmap, plan->n_words)) ||
       (rc = dev_alloc_n(&plan->word_off, plan->n_words)) ||
       (rc = dev_alloc_n(&plan->unique_cols, std::max<int64_t>(std::min(plan->nnz, n_cols), 1))) ||
@@ -559,6 +568,7 @@ SHIRO_API int shiro_prepare(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t
   }
   if (ops & SHIRO_OP_BACKWARD) {
     SHIRO_TRY(build_transposed(plan, s));
+    SHIRO_TRY(ensure_tvals(plan, true));
     const shiro_tuning_t t = tuning_for(plan, SHIRO_KERNEL_SPMM_T, N, dt);
     SHIRO_TRY(ensure_cols_work(plan, t.chunk, true, s, &wl));
     SHIRO_TRY(ensure_carry(plan, (int64_t)wl->W * 2 * N, true));

@@ -17,6 +17,9 @@ struct WorkList {
   int32_t W = 0;
   int32_t* chunk_row = nullptr;  // W + 1
   int32_t* chunk_nz = nullptr;   // W + 1
+  // rows cut by chunk boundaries: (first chunk, last chunk, row) triples
+  int32_t nsplit = 0;
+  int32_t* split = nullptr;      // 3 * nsplit
 };
 
 // Transposed pattern of the remapped panel: packed column u's nonzeros,
@@ -62,6 +65,7 @@ struct shiro_plan_s {
   bool selected = false;
   int64_t U = -1;
   int64_t n_words = 0;
+  uint8_t* flags = nullptr;     // 32 * n_words: 1 if the column id occurs in the panel
   uint32_t* bitmap = nullptr;   // n_words
   int32_t* word_off = nullptr;  // n_words: exclusive prefix of popcounts
   int32_t* unique_cols = nullptr;  // capacity min(nnz, n_cols)
@@ -78,6 +82,10 @@ struct shiro_plan_s {
   // carry slots of split rows: 2 * W * carry_cols floats
   float* carry = nullptr;
   int64_t carry_elems = 0;
+
+  // values in transposed order (gathered per backward call)
+  float* tvals = nullptr;
+  int64_t tvals_elems = 0;
 
   // float32 accumulator of the per-block mode when Y is bfloat16
   float* acc32 = nullptr;
@@ -161,6 +169,7 @@ int ensure_cols_work(shiro_plan plan, int32_t chunk, bool allocate, hipStream_t 
                      const WorkList** out);
 int ensure_carry(shiro_plan plan, int64_t elems, bool allocate);
 int ensure_acc32(shiro_plan plan, int64_t elems, bool allocate);
+int ensure_tvals(shiro_plan plan, bool allocate);
 
 shiro_tuning_t default_tuning(int kernel, int32_t N, shiro_dtype dt);
 int validate_tuning(int kernel, int32_t N, shiro_dtype dt, const shiro_tuning_t& t);

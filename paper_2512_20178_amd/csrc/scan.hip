@@ -36,7 +36,7 @@ struct OutI64 {
 };
 }  // namespace
 
-int64_t scan_scratch_bytes(int64_t n) { return scan_tiles_of(n > 0 ? n : 1) * 8 + 256; }
+int64_t scan_scratch_bytes(int64_t n) { return scan_tiles_of(n > 0 ? n : 1, 1) * 8 + 256; }
 
 int exclusive_scan_i32_to_i64(const int32_t* in, int64_t n, int64_t* out, int64_t* d_total,
                               void* scratch, hipStream_t s) {

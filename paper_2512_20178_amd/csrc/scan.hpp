@@ -9,8 +9,7 @@
 
 namespace shiro {
 
-constexpr int kScanItems = 16;                    // elements per thread
-constexpr int kScanTile = kBlock * kScanItems;    // 4096 elements per workgroup
+constexpr int kScanItems = 16;                    // default elements per thread
 
 template <typename T>
 __device__ __forceinline__ T wave_inclusive_scan(T x) {
@@ -43,13 +42,13 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* lds, T* total) {
   return off + inc - v;
 }
 
-template <class In>
+template <int ITEMS, class In>
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(In in, int64_t n, int64_t* tile_sums) {
   __shared__ int64_t lds[kWavesPerBlock];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  const int64_t base = (int64_t)blockIdx.x * (kBlock * ITEMS) + (int64_t)threadIdx.x * ITEMS;
   int64_t s = 0;
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i)
+  for (int i = 0; i < ITEMS; ++i)
     if (base + i < n) s += in(base + i);
   int64_t tot;
   block_exclusive_scan<int64_t>(s, lds, &tot);
@@ -60,21 +59,21 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(In in, int64_t n, int64_
 __global__ __launch_bounds__(kBlock) void k_scan_tiles(int64_t* sums, int64_t ntiles,
                                                        int64_t* d_total);
 
-template <class In, class Out>
+template <int ITEMS, class In, class Out>
 __global__ __launch_bounds__(kBlock) void k_scan_down(In in, int64_t n, const int64_t* tile_off,
                                                       Out out) {
   __shared__ int64_t lds[kWavesPerBlock];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  int64_t v[kScanItems];
+  const int64_t base = (int64_t)blockIdx.x * (kBlock * ITEMS) + (int64_t)threadIdx.x * ITEMS;
+  int64_t v[ITEMS];
   int64_t s = 0;
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
+  for (int i = 0; i < ITEMS; ++i) {
     v[i] = (base + i < n) ? in(base + i) : 0;
     s += v[i];
   }
   int64_t ex = block_exclusive_scan<int64_t>(s, lds, nullptr) + tile_off[blockIdx.x];
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
+  for (int i = 0; i < ITEMS; ++i) {
     if (base + i < n) out(base + i, ex, v[i]);
     ex += v[i];
   }
@@ -82,10 +81,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(In in, int64_t n, const in
 
 __global__ void k_set_i64(int64_t* p, int64_t v);
 
-inline int64_t scan_tiles_of(int64_t n) { return ceil_div(n, kScanTile); }
+inline int64_t scan_tiles_of(int64_t n, int items = kScanItems) { return ceil_div(n, (int64_t)kBlock * items); }
 
-// Host driver.  scratch must hold scan_tiles_of(n) int64.
-template <class In, class Out>
+// Host driver.  scratch must hold scan_tiles_of(n, ITEMS) int64.
+template <int ITEMS = kScanItems, class In, class Out>
 int scan_generic(In in, int64_t n, Out out, int64_t* d_total, void* scratch, hipStream_t s) {
   if (n <= 0) {
     if (d_total) {
@@ -94,13 +93,13 @@ int scan_generic(In in, int64_t n, Out out, int64_t* d_total, void* scratch, hip
     }
     return SHIRO_OK;
   }
-  const int64_t ntiles = scan_tiles_of(n);
+  const int64_t ntiles = scan_tiles_of(n, ITEMS);
   int64_t* sums = reinterpret_cast<int64_t*>(scratch);
-  k_scan_reduce<In><<<dim3((unsigned)ntiles), kBlock, 0, s>>>(in, n, sums);
+  k_scan_reduce<ITEMS, In><<<dim3((unsigned)ntiles), kBlock, 0, s>>>(in, n, sums);
   SHIRO_LAUNCH_CHECK();
   k_scan_tiles<<<1, kBlock, 0, s>>>(sums, ntiles, d_total);
   SHIRO_LAUNCH_CHECK();
-  k_scan_down<In, Out><<<dim3((unsigned)ntiles), kBlock, 0, s>>>(in, n, sums, out);
+  k_scan_down<ITEMS, In, Out><<<dim3((unsigned)ntiles), kBlock, 0, s>>>(in, n, sums, out);
   SHIRO_LAUNCH_CHECK();
   return SHIRO_OK;
 }

@@ -1,11 +1,14 @@
 // Panel extraction and Cols(A^(p,q)) selection.
 //
 // Selection (Table 1; Sec. 3.1 column-based scheme; Sec. 5.1 stage 1) runs
-// over the whole panel at once: one bit per global column id marks the
-// columns present in the panel, a prefix sum of the per-word popcounts gives
-// every present column its packed position, and because column blocks are
-// contiguous id ranges the positions are already grouped block by block in
-// ascending id order.  block_off[q] is the rank of block q's first column id.
+// over the whole panel at once: one flag byte per global column id marks the
+// columns present in the panel (plain byte stores of 1: idempotent, no
+// atomics, so they stay in each XCD's L2 and merge by byte mask on
+// write-back), the flags are folded into one bit per id, a prefix sum of the
+// per-word popcounts gives every present column its packed position, and
+// because column blocks are contiguous id ranges the positions are already
+// grouped block by block in ascending id order.  block_off[q] is the rank of
+// block q's first column id.
 #include "plan.hpp"
 #include "scan.hpp"
 
@@ -18,12 +21,6 @@ __global__ void k_rebase(const int64_t* __restrict__ src, int64_t n, int64_t* __
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = src[i] - base;
-}
-
-__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = v;
 }
 
 __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
@@ -88,18 +85,42 @@ __global__ void k_block_nnz_global(const int32_t* __restrict__ col, int64_t nnz,
     atomicAdd(&out[(int64_t)col[k] / K], 1ull);
 }
 
-// Mark the column ids present in the panel.  The bit is read from L2 first
-// (device-scope load, bypassing the per-CU cache) and the atomic OR is issued
-// only if it is still clear, so hub columns cost a read, not an atomic.  The
-// final bitmap is the set union, independent of ordering.
-__global__ void k_mark(const int32_t* __restrict__ col, int64_t nnz, uint32_t* bitmap) {
+// flag[c] = 1 for every column id c of the panel.
+__global__ void k_mark(const int32_t* __restrict__ col, int64_t nnz, uint8_t* __restrict__ flag) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t c = (uint32_t)col[k];
-    const uint32_t bit = 1u << (c & 31u);
-    uint32_t* w = bitmap + (c >> 5);
-    const uint32_t cur = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (!(cur & bit)) atomicOr(w, bit);
+       k += (int64_t)gridDim.x * blockDim.x)
+    flag[col[k]] = 1;
+}
+
+// Zero the flag bytes (16 bytes per store; the tail byte by byte).
+__global__ void k_zero_bytes(uint8_t* __restrict__ p, int64_t n) {
+  const int64_t n16 = n >> 4;
+  u32x4 z = {0u, 0u, 0u, 0u};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n16;
+       i += (int64_t)gridDim.x * blockDim.x)
+    reinterpret_cast<u32x4*>(p)[i] = z;
+  for (int64_t i = (n16 << 4) + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+// bitmap[w] bit b = flag[32 w + b] (the flag array is padded to whole words).
+__global__ void k_fold_flags(const uint8_t* __restrict__ flag, int64_t n_words,
+                             uint32_t* __restrict__ bitmap) {
+  for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < n_words;
+       w += (int64_t)gridDim.x * blockDim.x) {
+    const u32x4* f = reinterpret_cast<const u32x4*>(flag + (w << 5));
+    const u32x4 a = f[0], b = f[1];
+    const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      // each byte is 0 or 1: gather bit 0 of the four bytes of v[i]
+      const uint32_t x = v[i];
+      const uint32_t q = (x & 1u) | ((x >> 7) & 2u) | ((x >> 14) & 4u) | ((x >> 21) & 8u);
+      m |= q << (4 * i);
+    }
+    bitmap[w] = m;
   }
 }
 
@@ -198,17 +219,19 @@ int run_select(shiro_plan plan, hipStream_t s, bool sync) {
   const int64_t nw = plan->n_words;
   const int64_t nnz = plan->nnz;
   // scratch: [U (int64)] [scan tile sums]
-  SHIRO_TRY(ensure_scratch(plan, 256 + scan_scratch_bytes(nw)));
+  SHIRO_TRY(ensure_scratch(plan, 256 + scan_scratch_bytes(nw)));  // (sized for 1 item per thread)
   int64_t* d_U = reinterpret_cast<int64_t*>(plan->scratch);
   void* scan_tmp = reinterpret_cast<char*>(plan->scratch) + 256;
 
-  k_fill_u32<<<grid_for(nw), kBlock, 0, s>>>(plan->bitmap, nw, 0u);
+  k_zero_bytes<<<grid_for(ceil_div(nw * 32, 16), 16384), kBlock, 0, s>>>(plan->flags, nw * 32);
   SHIRO_LAUNCH_CHECK();
   if (nnz > 0) {
-    k_mark<<<grid_for(nnz), kBlock, 0, s>>>(plan->col, nnz, plan->bitmap);
+    k_mark<<<grid_for(nnz), kBlock, 0, s>>>(plan->col, nnz, plan->flags);
     SHIRO_LAUNCH_CHECK();
   }
-  SHIRO_TRY(scan_generic(PopcountIn{plan->bitmap}, nw,
+  k_fold_flags<<<grid_for(nw), kBlock, 0, s>>>(plan->flags, nw, plan->bitmap);
+  SHIRO_LAUNCH_CHECK();
+  SHIRO_TRY(scan_generic<4>(PopcountIn{plan->bitmap}, nw,
                          CompactOut{plan->bitmap, plan->word_off, plan->unique_cols}, d_U,
                          scan_tmp, s));
   if (nnz > 0) {

@@ -42,6 +42,48 @@ __global__ void k_merge_path(const int64_t* __restrict__ ptr, int32_t R, int64_t
   chunk_nz[w] = (int32_t)(d - lo);
 }
 
+// flag[w] = 1 if chunk w starts a row that a later chunk finishes.
+__global__ void k_split_flags(const int64_t* __restrict__ ptr, int32_t R,
+                              const int32_t* __restrict__ chunk_row,
+                              const int32_t* __restrict__ chunk_nz, int32_t W,
+                              int32_t* __restrict__ flag) {
+  const int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  const int32_t r = chunk_row[w + 1];
+  int32_t f = 0;
+  if (r < R) {
+    const int64_t rs = ptr[r];
+    f = (chunk_nz[w + 1] > rs) && (rs >= chunk_nz[w]);
+  }
+  flag[w] = f;
+}
+
+// split[3 pos[w] ..] = (w, last chunk holding row r, r) for flagged chunks.
+__global__ void k_split_emit(const int32_t* __restrict__ flag, const int64_t* __restrict__ pos,
+                             const int32_t* __restrict__ chunk_row, int32_t W,
+                             int32_t* __restrict__ split) {
+  const int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (w >= W || !flag[w]) return;
+  const int32_t r = chunk_row[w + 1];
+  // last chunk we with chunk_row[we] <= r, i.e. the first with chunk_row[we + 1] > r
+  int64_t lo = w + 1, hi = W - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (chunk_row[mid + 1] > r) hi = mid; else lo = mid + 1;
+  }
+  const int64_t s = pos[w];
+  split[3 * s] = (int32_t)w;
+  split[3 * s + 1] = (int32_t)lo;
+  split[3 * s + 2] = r;
+}
+
+__global__ void k_gather_vals(const int32_t* __restrict__ perm, const float* __restrict__ vals,
+                              int64_t nnz, float* __restrict__ out) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nnz;
+       j += (int64_t)gridDim.x * blockDim.x)
+    out[j] = vals[perm[j]];
+}
+
 // ---------------------------------------------------------------------------
 // SpMM: out[r, :] = sum_{k in row r} vals[perm ? perm[k] : k] * X[idx[k], :]
 // ---------------------------------------------------------------------------
@@ -181,30 +223,46 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
   }
 }
 
-// Rows split over chunks: sum the tail slot of the starting chunk and the
-// head slots of the following chunks, in chunk order, then the epilogue.
+// Rows cut by chunk boundaries.  split[3 i] = first chunk ws, split[3 i + 1]
+// = last chunk we, split[3 i + 2] = row r.  The row's pieces are the tail
+// slot of ws and the head slots of ws+1 .. we.  One workgroup per row:
+// slice s of the workgroup sums pieces s, s + S, s + 2S, ... in order, then
+// slice 0 adds the S slice sums in order and applies the epilogue once.
 template <typename TIN, typename TOUT, int VEC>
-__global__ __launch_bounds__(kBlock) void k_fixup(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
-  const int lane = lane_id();
-  const int32_t nwaves = gridDim.x * kWavesPerBlock;
-  for (int32_t w = uniform((int32_t)blockIdx.x * kWavesPerBlock + wave_id()); w < W; w += nwaves) {
-    const int32_t r = chunk_row[w + 1];
-    if (r >= R) continue;
-    const int64_t rs = ptr[r];
-    const int64_t j0 = chunk_nz[w], j1 = chunk_nz[w + 1];
-    // chunk w starts row r (no earlier part) and does not finish it
-    if (!(j1 > rs && rs >= j0)) continue;
-    for (int64_t c = (int64_t)lane * VEC; c < N; c += (int64_t)kWave * VEC) {
+__global__ __launch_bounds__(kBlock) void k_fixup(SHIRO_SPMM_PARAMS(TIN, TOUT),
+                                                  const int32_t* __restrict__ split, int32_t nsplit) {
+  __shared__ float part[kBlock * VEC];
+  const int32_t lanes_per_row = (int32_t)min((int64_t)kBlock, ((int64_t)N + VEC - 1) / VEC);
+  const int32_t S = kBlock / lanes_per_row;  // slices (pieces summed in parallel)
+  const int32_t t = threadIdx.x;
+  const int32_t sl = t / lanes_per_row, li = t % lanes_per_row;
+  for (int32_t i = blockIdx.x; i < nsplit; i += gridDim.x) {
+    const int32_t ws = split[3 * i], we = split[3 * i + 1], r = split[3 * i + 2];
+    const int32_t np = we - ws + 1;
+    for (int64_t c0 = 0; c0 < N; c0 += (int64_t)lanes_per_row * VEC) {
+      const int64_t c = c0 + (int64_t)li * VEC;
       float acc[VEC];
-      Elem<float>::template load<VEC>(carry + ((int64_t)w * 2 + 1) * N + c, acc);
-      for (int32_t w2 = w + 1;; ++w2) {
-        float p[VEC];
-        Elem<float>::template load<VEC>(carry + ((int64_t)w2 * 2) * N + c, p);
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[e] += p[e];
-        if (chunk_row[w2 + 1] > r) break;
+      for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
+      if (sl < S && c < N) {
+        for (int32_t q = sl; q < np; q += S) {
+          const int64_t slot = q == 0 ? (int64_t)ws * 2 + 1 : (int64_t)(ws + q) * 2;
+          float p[VEC];
+          Elem<float>::template load<VEC>(carry + slot * N + c, p);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) acc[e] += p[e];
+        }
       }
-      epilogue_row<TOUT, VEC>(out, ldo, scat, lds, scat_idx, r, c, acc);
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) part[t * VEC + e] = acc[e];
+      __syncthreads();
+      if (sl == 0 && c < N) {
+        for (int32_t q = 1; q < S; ++q)
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) acc[e] += part[(q * lanes_per_row + li) * VEC + e];
+        epilogue_row<TOUT, VEC>(out, ldo, scat, lds, scat_idx, r, c, acc);
+      }
     }
   }
 }
@@ -593,11 +651,12 @@ int run_spmm_family(shiro_plan plan, shiro_tuning_t t, const WorkList* wl, SpmmA
     if (vec == V16) SHIRO_TRY((spmm_dispatch<TIN, TOUT, V16, false>(t, grid, s, a)));
     else SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1, false>(t, grid, s, a)));
   }
-  const unsigned fb = grid_for((int64_t)wl->W * kWave, 4096);
+  if (wl->nsplit == 0) return SHIRO_OK;
+  const unsigned fb = (unsigned)std::min<int64_t>(wl->nsplit, 65536);
   if (vec == V16 && (a.N % 4) == 0) {
-    k_fixup<TIN, TOUT, 4><<<fb, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a));
+    k_fixup<TIN, TOUT, 4><<<fb, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a), wl->split, wl->nsplit);
   } else {
-    k_fixup<TIN, TOUT, 1><<<fb, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a));
+    k_fixup<TIN, TOUT, 1><<<fb, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a), wl->split, wl->nsplit);
   }
   SHIRO_LAUNCH_CHECK();
   return SHIRO_OK;
@@ -617,6 +676,48 @@ int build_worklist(const int64_t* ptr, int64_t R, int64_t nnz, int32_t chunk, Wo
   k_merge_path<<<grid_for((int64_t)wl->W + 1, 1 << 20), kBlock, 0, s>>>(
       ptr, (int32_t)R, nnz, chunk, wl->W, wl->chunk_row, wl->chunk_nz);
   SHIRO_LAUNCH_CHECK();
+  wl->nsplit = 0;
+  if (wl->W == 0) return SHIRO_OK;
+  // list of rows cut by chunk boundaries (temporary buffers, freed here)
+  int32_t* flag = nullptr;
+  int64_t* pos = nullptr;
+  void* tmp = nullptr;
+  int64_t* h_n = nullptr;
+  auto cleanup = [&] {
+    dev_free(flag);
+    dev_free(pos);
+    dev_free(tmp);
+    if (h_n) (void)hipHostFree(h_n);
+  };
+  int rc;
+  if ((rc = dev_alloc_n(&flag, wl->W)) || (rc = dev_alloc_n(&pos, (int64_t)wl->W + 1)) ||
+      (rc = dev_alloc(&tmp, scan_scratch_bytes(wl->W)))) {
+    cleanup();
+    return rc;
+  }
+  if (hipHostMalloc((void**)&h_n, 8, hipHostMallocDefault) != hipSuccess) {
+    cleanup();
+    return set_error(SHIRO_ERR_OOM, "work list: pinned allocation failed");
+  }
+  k_split_flags<<<grid_for(wl->W, 1 << 20), kBlock, 0, s>>>(ptr, (int32_t)R, wl->chunk_row,
+                                                            wl->chunk_nz, wl->W, flag);
+  if ((rc = exclusive_scan_i32_to_i64(flag, wl->W, pos, pos + wl->W, tmp, s)) ||
+      hipMemcpyAsync(h_n, pos + wl->W, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    cleanup();
+    return rc ? rc : set_error(SHIRO_ERR_HIP, "work list: split count failed");
+  }
+  wl->nsplit = (int32_t)*h_n;
+  if (wl->nsplit > 0) {
+    if ((rc = dev_alloc_n(&wl->split, 3 * (int64_t)wl->nsplit))) {
+      cleanup();
+      return rc;
+    }
+    k_split_emit<<<grid_for(wl->W, 1 << 20), kBlock, 0, s>>>(flag, pos, wl->chunk_row, wl->W, wl->split);
+  }
+  const hipError_t e = hipStreamSynchronize(s);
+  cleanup();
+  if (e != hipSuccess) return set_error(SHIRO_ERR_HIP, "work list: split list failed");
   return SHIRO_OK;
 }
 
@@ -809,13 +910,20 @@ int launch_spmm_t(shiro_plan plan, const shiro_tuning_t& t, const float* vals, c
     SHIRO_TRY(build_transposed(plan, s));
   }
   const WorkList* wl;
-  SHIRO_TRY(ensure_cols_work(plan, t.chunk, !stream_capturing(s), s, &wl));
-  SHIRO_TRY(ensure_carry(plan, (int64_t)wl->W * 2 * N, !stream_capturing(s)));
+  const bool cap = stream_capturing(s);
+  SHIRO_TRY(ensure_cols_work(plan, t.chunk, !cap, s, &wl));
+  SHIRO_TRY(ensure_carry(plan, (int64_t)wl->W * 2 * N, !cap));
+  SHIRO_TRY(ensure_tvals(plan, !cap));
+  // values in transposed order: one streaming gather per call, so the hot
+  // loop reads them contiguously instead of through a dependent index
+  k_gather_vals<<<grid_for(plan->nnz), kBlock, 0, s>>>(plan->tr.perm, vals + plan->nz_begin, plan->nnz,
+                                                        plan->tvals);
+  SHIRO_LAUNCH_CHECK();
   SpmmArgs a{};
   a.ptr = plan->tr.ptr;
   a.idx = plan->tr.row;
-  a.perm = plan->tr.perm;
-  a.vals = vals + plan->nz_begin;
+  a.perm = nullptr;
+  a.vals = plan->tvals;
   a.X = dY;
   a.ldx = lddy;
   a.out = dBp;
