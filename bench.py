@@ -163,19 +163,21 @@ def main():
     sz = 4 if tdt == torch.float32 else 2
     rp = A.row_ptr[info["row_begin"]: info["row_begin"] + M + 1]
     R_nonempty = int((rp[1:] != rp[:-1]).sum().item())
+    # algorithmic bytes: every B / Bpacked / dY row read once, every output row
+    # written once, 8 bytes of index + value per nonzero (SURVEY-style counts)
     alg = {
         "select": 8 * nnz + 4 * U + 2 * ((A.n_cols + 7) // 8),
         "pack_B": 2 * U * N * sz,
         "spmm": 8 * (M + 1) + 8 * nnz + U * N * sz + M * N * sz,
-        "spmm_t": 8 * (U + 1) + 8 * nnz + R_nonempty * N * sz + U * N * sz + 2 * U * N * sz,
-        "sddmm": 8 * (M + 1) + 8 * nnz + R_nonempty * N * sz + U * N * sz,
+        # A^T dY -> dBpacked, add-scatter into dB, dvals, in one pass over the transposed pattern
+        "backward": 8 * (U + 1) + 8 * nnz + 4 * nnz + R_nonempty * N * sz + U * N * sz
+        + U * N * sz + 2 * U * N * sz,
     }
     ops = {
         "select": lambda: shiro.refresh_selection(plan),
         "pack_B": lambda: shiro.pack_B(plan, B, out=Bp),
         "spmm": lambda: shiro.spmm(plan, vals, Bp, out=Y),
-        "spmm_t": lambda: shiro.spmm_backward(plan, vals, G, None, dBpacked=dBp, dB=dB),
-        "sddmm": lambda: shiro.spmm_backward(plan, vals, G, Bp, dvals=dvals),
+        "backward": lambda: shiro.spmm_backward(plan, vals, G, Bp, dBpacked=dBp, dB=dB, dvals=dvals),
     }
     reps = 10
     kern_us = {}
@@ -191,9 +193,9 @@ def main():
         torch.cuda.synchronize()
         kern_us[name] = float(np.mean([a.elapsed_time(b) for a, b in evs]) * 1e3)
     log("per-call us: " + ", ".join(f"{k}={v:.1f}" for k, v in kern_us.items()))
-    alg_step = alg["select"] + alg["pack_B"] + alg["spmm"] + alg["spmm_t"] + alg["sddmm"]
+    alg_step = sum(alg.values())
 
-    dom = max(("pack_B", "spmm", "spmm_t", "sddmm"), key=lambda k: kern_us[k])
+    dom = max(("pack_B", "spmm", "backward"), key=lambda k: kern_us[k])
     achieved = alg[dom] / (kern_us[dom] * 1e-6) / 1e9
     traffic = None
     pmc_path = os.path.join(ROOT, "profiles", f"pmc_{dom}_{args.workload}_N{N}_{args.dtype}.json")
@@ -202,7 +204,9 @@ def main():
             pmc = json.load(f)
         if pmc.get("src_hash") == src_hash("spmm.hip", "common.hpp"):
             traffic = pmc.get("hbm_bytes_per_launch")
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+    kernels_of = {"pack_B": "k_pack", "spmm": "k_spmm + k_fixup",
+                  "backward": "k_gather_vals + k_spmm<dot> + k_fixup + k_scatter_vals"}
+    roofline = {"bound": "hbm", "kernel": f"{dom} ({kernels_of[dom]})", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes": int(alg[dom]), "duration_us": round(kern_us[dom], 2)}
 
@@ -228,12 +232,19 @@ def main():
         "setup_ms": {"partition": round(t_part * 1e3, 2), "select_rows": round(t_sel * 1e3, 2)},
     }
 
-    if args.calib_copy:
-        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
+    # achievable bandwidth of a plain device copy (1 GiB read + 1 GiB written)
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(1 if args.calib_copy else 5):
         dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    b.record()
+    torch.cuda.synchronize()
+    out["copy_GBs"] = round(2 * src.numel() * 4 / (a.elapsed_time(b) / (1 if args.calib_copy else 5) * 1e-3) / 1e9, 1)
+    del src, dst
 
     if not args.no_extras:
         # batched (one launch, row-merged) vs one launch per column block
@@ -270,9 +281,17 @@ def main():
                 shiro.spmm(plan, vals, Bph, out=Yh)
                 shiro.spmm_backward(plan, vals, Gh, Bph, dBpacked=dBph, dB=dBh, dvals=dvals)
 
+            if not args.no_autotune:
+                shiro.autotune(plan, N, torch.bfloat16, ops=("spmm", "backward"))
             t_bf = timed(step_bf16)
             out["bf16_step_us"] = round(t_bf, 2)
             out["bf16_speedup"] = round(ms_step * 1e3 / t_bf, 3)
+            out["bf16_kernels_us"] = {
+                "pack_B": round(timed(lambda: shiro.pack_B(plan, Bh, out=Bph)), 2),
+                "spmm": round(timed(lambda: shiro.spmm(plan, vals, Bph, out=Yh)), 2),
+                "backward": round(timed(lambda: shiro.spmm_backward(plan, vals, Gh, Bph, dBpacked=dBph, dB=dBh,
+                                                                    dvals=dvals)), 2),
+            }
             del Bh, Gh, Bph, Yh, dBph, dBh
         # sampled parity of Y at full size against the FP64 oracle
         import oracle

@@ -113,6 +113,7 @@ int ensure_tvals(shiro_plan plan, bool allocate) {
   if (plan->tvals_elems >= plan->nnz && plan->tvals) return SHIRO_OK;
   if (!allocate) return set_error(SHIRO_ERR_CAPTURING, "transposed values buffer not prepared before capture");
   SHIRO_TRY(dev_alloc_n(&plan->tvals, std::max<int64_t>(plan->nnz, 1)));
+  SHIRO_TRY(dev_alloc_n(&plan->tdvals, std::max<int64_t>(plan->nnz, 1)));
   plan->tvals_elems = plan->nnz;
   return SHIRO_OK;
 }
@@ -175,6 +176,7 @@ static void plan_free(shiro_plan plan) {
       dev_free(kv.second.split);
     }
   dev_free(plan->tvals);
+  dev_free(plan->tdvals);
   dev_free(plan->tr.ptr);
   dev_free(plan->tr.row);
   dev_free(plan->tr.perm);
@@ -287,7 +289,8 @@ static int tune_one(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt, Tune
     if (kernel == SHIRO_KERNEL_SPMM)
       return launch_spmm(plan, t, b.vals, b.Bp, N, N, dt, b.Y, N, dt == SHIRO_F32 ? SHIRO_F32 : SHIRO_BF16, s);
     if (kernel == SHIRO_KERNEL_SPMM_T)
-      return launch_spmm_t(plan, t, b.vals, b.dY, N, N, dt, b.dBp, N, nullptr, 0, s);
+      return launch_spmm_t(plan, t, b.vals, b.dY, N, N, dt, b.dBp, N, nullptr, 0, b.Bp, N, b.dvals,
+                           nullptr, s);
     return launch_sddmm(plan, t, b.vals, b.dY, N, b.Bp, N, N, dt, b.dvals, s);
   };
   shiro_tuning_t best = default_tuning(kernel, N, dt);
@@ -539,10 +542,11 @@ SHIRO_API int shiro_spmm_backward(shiro_plan plan, const float* d_vals, const vo
     if (d_dvals && !d_Bpacked) return set_error(SHIRO_ERR_INVALID_ARG, "spmm_backward: d_Bpacked is NULL");
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  bool dvals_done = false;
   if (d_dBpacked || d_dB)
     SHIRO_TRY(launch_spmm_t(plan, tuning_for(plan, SHIRO_KERNEL_SPMM_T, N, dt), d_vals, d_dY, lddy, N,
-                            dt, d_dBpacked, lddbp, d_dB, lddb, s));
-  if (d_dvals) {
+                            dt, d_dBpacked, lddbp, d_dB, lddb, d_Bpacked, ldp, d_dvals, &dvals_done, s));
+  if (d_dvals && !dvals_done) {
     if (N == 0) {
       // dvals of an empty product are zero
       return set_error(SHIRO_ERR_INVALID_ARG, "spmm_backward: dvals needs N >= 1");

@@ -83,8 +83,9 @@ struct shiro_plan_s {
   float* carry = nullptr;
   int64_t carry_elems = 0;
 
-  // values in transposed order (gathered per backward call)
+  // values and value gradients in transposed order (per backward call)
   float* tvals = nullptr;
+  float* tdvals = nullptr;
   int64_t tvals_elems = 0;
 
   // float32 accumulator of the per-block mode when Y is bfloat16
@@ -153,9 +154,12 @@ int launch_spmm(shiro_plan plan, const shiro_tuning_t& t, const float* vals, con
 int launch_spmm_per_block(shiro_plan plan, const float* vals, const void* X, int64_t ldx,
                           int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy, shiro_dtype out_dt,
                           hipStream_t s);
+// A^T dY into dBpacked and/or dB.  When dvals is given and one column tile
+// covers N, the value gradients are computed in the same pass (*dvals_done).
 int launch_spmm_t(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* dY,
                   int64_t lddy, int32_t N, shiro_dtype dt, void* dBp, int64_t lddbp, void* dB,
-                  int64_t lddb, hipStream_t s);
+                  int64_t lddb, const void* Bp, int64_t ldp, float* dvals, bool* dvals_done,
+                  hipStream_t s);
 int launch_sddmm(shiro_plan plan, const shiro_tuning_t& t, const float* vals_unused,
                  const void* dY, int64_t lddy, const void* Bp, int64_t ldp, int32_t N,
                  shiro_dtype dt, float* dvals, hipStream_t s);

@@ -84,8 +84,15 @@ __global__ void k_gather_vals(const int32_t* __restrict__ perm, const float* __r
     out[j] = vals[perm[j]];
 }
 
+__global__ void k_scatter_vals(const int32_t* __restrict__ perm, const float* __restrict__ in,
+                               int64_t nnz, float* __restrict__ out) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nnz;
+       j += (int64_t)gridDim.x * blockDim.x)
+    out[perm[j]] = in[j];
+}
+
 // ---------------------------------------------------------------------------
-// SpMM: out[r, :] = sum_{k in row r} vals[perm ? perm[k] : k] * X[idx[k], :]
+// SpMM: out[r, :] = sum_{k in row r} vals[k] * X[idx[k], :]
 // ---------------------------------------------------------------------------
 // Host-side bundle of the kernel arguments.  The kernels take them as
 // separate __restrict__ parameters: that tells the compiler the pattern
@@ -94,8 +101,10 @@ __global__ void k_gather_vals(const int32_t* __restrict__ perm, const float* __r
 struct SpmmArgs {
   const int64_t* ptr;       // R + 1
   const int32_t* idx;       // nnz: row of X to gather
-  const int32_t* perm;      // nnz or null: value index
-  const float* vals;        // values (panel-local indexing)
+  const float* vals;        // values in pattern order
+  const void* D;            // optional: dense row per pattern row, dotted with each gathered row
+  int64_t ldd;
+  float* dot_out;           // nnz: the dots, in pattern order (when D is set)
   const void* X;            // gathered dense rows
   int64_t ldx;
   void* out;                // R x N, may be null (transposed: dBpacked optional)
@@ -113,14 +122,16 @@ struct SpmmArgs {
 
 #define SHIRO_SPMM_PARAMS(TIN, TOUT)                                                          \
   const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,                           \
-      const int32_t *__restrict__ perm, const float *__restrict__ vals,                       \
+      const float *__restrict__ vals, const TIN *__restrict__ D, int64_t ldd,                 \
+      float *__restrict__ dot_out,                                                            \
       const TIN *__restrict__ X, int64_t ldx, TOUT *__restrict__ out, int64_t ldo,           \
       TOUT *__restrict__ scat, int64_t lds, const int32_t *__restrict__ scat_idx,             \
       const int32_t *__restrict__ chunk_row, const int32_t *__restrict__ chunk_nz,            \
       float *__restrict__ carry, int32_t W, int32_t R, int32_t N, int32_t cpw, int32_t xcd_remap
 
 #define SHIRO_SPMM_ARGS(TIN, TOUT, a)                                                          \
-  (a).ptr, (a).idx, (a).perm, (a).vals, reinterpret_cast<const TIN*>((a).X), (a).ldx,          \
+  (a).ptr, (a).idx, (a).vals, reinterpret_cast<const TIN*>((a).D), (a).ldd, (a).dot_out,      \
+      reinterpret_cast<const TIN*>((a).X), (a).ldx,                                            \
       reinterpret_cast<TOUT*>((a).out), (a).ldo, reinterpret_cast<TOUT*>((a).scat), (a).lds,   \
       (a).scat_idx, (a).chunk_row, (a).chunk_nz, (a).carry, (a).W, (a).R, (a).N,               \
       (a).chunks_per_wave, (a).xcd_remap
@@ -149,7 +160,11 @@ __device__ __forceinline__ int32_t logical_block(int32_t remap) {
   return (b & 7) * (g >> 3) + (b >> 3);
 }
 
-template <typename TIN, typename TOUT, int LANES, int VEC, int UNROLL, bool PERM>
+// With DOT (one column tile only), each gathered row is also dotted with the
+// pattern row's own dense row D[r]: in the transposed product this is the
+// gradient of the values, dvals = dY[row] . Bpacked[u], computed from the
+// same dY gathers (no second pass over the nonzeros).
+template <typename TIN, typename TOUT, int LANES, int VEC, int UNROLL, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
   constexpr int G = kWave / LANES;
   constexpr int STEP = G * UNROLL;
@@ -176,6 +191,12 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
       float acc[VEC];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
+      float d[VEC];
+      if constexpr (DOT) {
+        Elem<TIN>::template load<VEC>(D + (int64_t)r * ldd + cl, d);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) d[e] = cvalid ? d[e] : 0.f;
+      }
       for (int64_t k = kb; k < ke; k += STEP) {
         // Every slot loads (idle slots re-read the row's last nonzero, a
         // cache hit) so the loads of all slots are in flight together; the
@@ -189,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
           ok[u] = kk < ke;
           const int64_t kc = ok[u] ? kk : ke - 1;
           xi[u] = idx[kc];
-          v[u] = vals[PERM ? perm[kc] : kc];
+          v[u] = vals[kc];
         }
         float x[UNROLL][VEC];
 #pragma unroll
@@ -202,6 +223,17 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
             const float t = fmaf(v[u], x[u][e], acc[e]);
             acc[e] = ok[u] ? t : acc[e];
           }
+        if constexpr (DOT) {
+#pragma unroll
+          for (int u = 0; u < UNROLL; ++u) {
+            float q = 0.f;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) q = fmaf(d[e], x[u][e], q);
+#pragma unroll
+            for (int sft = 1; sft < LANES; sft <<= 1) q += __shfl_xor(q, sft, kWave);
+            if (li == 0 && ok[u]) dot_out[k + u * G + g] = q;
+          }
+        }
       }
       // combine the lane groups (fixed butterfly order)
 #pragma unroll
@@ -591,11 +623,11 @@ int grid_waves(shiro_plan plan, const shiro_tuning_t& t, int32_t W, int32_t* chu
   return SHIRO_OK;
 }
 
-template <typename TIN, typename TOUT, int VEC, bool PERM>
+template <typename TIN, typename TOUT, int VEC, bool DOT>
 int spmm_dispatch(const shiro_tuning_t& t, dim3 grid, hipStream_t s, const SpmmArgs& a) {
 #define SHIRO_SPMM_CASE(L, U)                                                               \
   if (t.lanes == L && t.unroll == U) {                                                      \
-    k_spmm<TIN, TOUT, L, VEC, U, PERM><<<grid, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a)); \
+    k_spmm<TIN, TOUT, L, VEC, U, DOT><<<grid, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a)); \
     SHIRO_LAUNCH_CHECK();                                                                   \
     return SHIRO_OK;                                                                        \
   }
@@ -644,7 +676,8 @@ int run_spmm_family(shiro_plan plan, shiro_tuning_t t, const WorkList* wl, SpmmA
   a.xcd_remap = t.xcd_remap;
   dim3 grid(nb, ntiles);
   constexpr int V16 = Elem<TIN>::kVec16;
-  if (a.perm) {
+  if (a.dot_out) {
+    if (ntiles != 1) return set_error(SHIRO_ERR_UNSUPPORTED, "fused dvals needs one column tile");
     if (vec == V16) SHIRO_TRY((spmm_dispatch<TIN, TOUT, V16, true>(t, grid, s, a)));
     else SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1, true>(t, grid, s, a)));
   } else {
@@ -873,7 +906,6 @@ int launch_spmm(shiro_plan plan, const shiro_tuning_t& t, const float* vals, con
   SpmmArgs a{};
   a.ptr = plan->row_ptr;
   a.idx = plan->colmap;
-  a.perm = nullptr;
   a.vals = vals + plan->nz_begin;
   a.X = X;
   a.ldx = ldx;
@@ -902,15 +934,16 @@ int launch_spmm(shiro_plan plan, const shiro_tuning_t& t, const float* vals, con
 
 int launch_spmm_t(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* dY,
                   int64_t lddy, int32_t N, shiro_dtype dt, void* dBp, int64_t lddbp, void* dB,
-                  int64_t lddb, hipStream_t s) {
+                  int64_t lddb, const void* Bp, int64_t ldp, float* dvals, bool* dvals_done,
+                  hipStream_t s) {
+  if (dvals_done) *dvals_done = false;
   if (plan->U == 0 || N == 0 || (!dBp && !dB)) return SHIRO_OK;
+  const bool cap = stream_capturing(s);
   if (!plan->tr.built) {
-    if (stream_capturing(s))
-      return set_error(SHIRO_ERR_CAPTURING, "backward: transposed pattern not prepared before capture");
+    if (cap) return set_error(SHIRO_ERR_CAPTURING, "backward: transposed pattern not prepared before capture");
     SHIRO_TRY(build_transposed(plan, s));
   }
   const WorkList* wl;
-  const bool cap = stream_capturing(s);
   SHIRO_TRY(ensure_cols_work(plan, t.chunk, !cap, s, &wl));
   SHIRO_TRY(ensure_carry(plan, (int64_t)wl->W * 2 * N, !cap));
   SHIRO_TRY(ensure_tvals(plan, !cap));
@@ -922,7 +955,6 @@ int launch_spmm_t(shiro_plan plan, const shiro_tuning_t& t, const float* vals, c
   SpmmArgs a{};
   a.ptr = plan->tr.ptr;
   a.idx = plan->tr.row;
-  a.perm = nullptr;
   a.vals = plan->tvals;
   a.X = dY;
   a.ldx = lddy;
@@ -937,11 +969,26 @@ int launch_spmm_t(shiro_plan plan, const shiro_tuning_t& t, const float* vals, c
   a.W = wl->W;
   a.R = (int32_t)plan->U;
   a.N = N;
-  if (dt == SHIRO_F32) {
-    const int v = vec_for<float>(N, {{dY, lddy}, {dBp, lddbp}, {dB, lddb}});
-    return run_spmm_family<float, float>(plan, t, wl, a, v, s);
+  int v;
+  if (dt == SHIRO_F32) v = vec_for<float>(N, {{dY, lddy}, {dBp, lddbp}, {dB, lddb}, {Bp, ldp}});
+  else v = vec_for<bf16_t>(N, {{dY, lddy}, {dBp, lddbp}, {dB, lddb}, {Bp, ldp}});
+  // dvals ride along when one column tile covers N
+  const bool fuse = dvals && Bp && (int64_t)effective_lanes(64, N, v) * v >= N;
+  if (fuse) {
+    shiro_tuning_t tt = t;
+    tt.lanes = 64;  // one tile
+    a.D = Bp;
+    a.ldd = ldp;
+    a.dot_out = plan->tdvals;
+    if (dt == SHIRO_F32) SHIRO_TRY((run_spmm_family<float, float>(plan, tt, wl, a, v, s)));
+    else SHIRO_TRY((run_spmm_family<bf16_t, bf16_t>(plan, tt, wl, a, v, s)));
+    k_scatter_vals<<<grid_for(plan->nnz), kBlock, 0, s>>>(plan->tr.perm, plan->tdvals, plan->nnz,
+                                                           dvals + plan->nz_begin);
+    SHIRO_LAUNCH_CHECK();
+    if (dvals_done) *dvals_done = true;
+    return SHIRO_OK;
   }
-  const int v = vec_for<bf16_t>(N, {{dY, lddy}, {dBp, lddbp}, {dB, lddb}});
+  if (dt == SHIRO_F32) return run_spmm_family<float, float>(plan, t, wl, a, v, s);
   return run_spmm_family<bf16_t, bf16_t>(plan, t, wl, a, v, s);
 }
 

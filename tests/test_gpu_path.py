@@ -201,6 +201,15 @@ def test_backward_f32(shiro, run):
     dvals2 = torch.zeros_like(dvals)
     shiro.spmm_backward(run.plan, run.Ad.vals, dY, Bp, dBpacked=dBp2, dvals=dvals2)
     assert torch.equal(dBp, dBp2) and torch.equal(dvals, dvals2)
+    # dvals alone (row-order SDDMM pass, no transposed product)
+    dvals3 = torch.zeros_like(dvals)
+    shiro.spmm_backward(run.plan, run.Ad.vals, dY, Bp, dvals=dvals3)
+    gv3 = dvals3.cpu().numpy()[run.Ac.nz_begin:run.Ac.nz_begin + run.Ac.nnz_panel]
+    assert oracle.rel_err(gv3, rdv, rdv_den) <= TOL_F32
+    # dB alone (transposed product without dBpacked and without dvals)
+    dB4 = torch.zeros(run.A.n_cols, run.N, device=dev)
+    shiro.spmm_backward(run.plan, run.Ad.vals, dY, None, dB=dB4)
+    assert oracle.rel_err(dB4.cpu().numpy()[run.uc], rdBp, rden) <= TOL_F32
 
 
 def test_backward_bf16(shiro, run):
