@@ -164,8 +164,7 @@ static void plan_free(shiro_plan plan) {
   dev_free(plan->row_ptr);
   dev_free(plan->col);
   dev_free(plan->flags);
-  dev_free(plan->bitmap);
-  dev_free(plan->word_off);
+  dev_free(plan->wtab);
   dev_free(plan->unique_cols);
   dev_free(plan->block_off);
   dev_free(plan->colmap);
@@ -396,8 +395,7 @@ SHIRO_API int shiro_partition(int64_t n_rows, int64_t n_cols, int64_t nnz, const
   if ((rc = dev_alloc_n(&plan->row_ptr, plan->rows + 1)) ||
       (rc = dev_alloc_n(&plan->col, std::max<int64_t>(plan->nnz, 1))) ||
       (rc = dev_alloc_n(&plan->flags, plan->n_words * 32)) ||
-      (rc = dev_alloc_n(&plan->bitmap, plan->n_words)) ||
-      (rc = dev_alloc_n(&plan->word_off, plan->n_words)) ||
+      (rc = dev_alloc_n(&plan->wtab, 2 * plan->n_words)) ||
       (rc = dev_alloc_n(&plan->unique_cols, std::max<int64_t>(std::min(plan->nnz, n_cols), 1))) ||
       (rc = dev_alloc_n(&plan->block_off, (int64_t)P + 1)) ||
       (rc = dev_alloc_n(&plan->colmap, std::max<int64_t>(plan->nnz, 1))))

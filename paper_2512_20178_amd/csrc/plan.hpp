@@ -66,8 +66,7 @@ struct shiro_plan_s {
   int64_t U = -1;
   int64_t n_words = 0;
   uint8_t* flags = nullptr;     // 32 * n_words: 1 if the column id occurs in the panel
-  uint32_t* bitmap = nullptr;   // n_words
-  int32_t* word_off = nullptr;  // n_words: exclusive prefix of popcounts
+  uint32_t* wtab = nullptr;     // 2 * n_words: (bits, exclusive prefix of popcounts) per word
   int32_t* unique_cols = nullptr;  // capacity min(nnz, n_cols)
   int64_t* block_off = nullptr;    // P + 1
   int32_t* colmap = nullptr;       // nnz

@@ -104,9 +104,11 @@ __global__ void k_zero_bytes(uint8_t* __restrict__ p, int64_t n) {
     p[i] = 0;
 }
 
-// bitmap[w] bit b = flag[32 w + b] (the flag array is padded to whole words).
+// Word table: wtab[2 w] = bits of word w (bit b = flag[32 w + b]; the flag
+// array is padded to whole words), wtab[2 w + 1] = packed position of the
+// word's first set bit.  Interleaved so that the remap reads one 8-byte entry.
 __global__ void k_fold_flags(const uint8_t* __restrict__ flag, int64_t n_words,
-                             uint32_t* __restrict__ bitmap) {
+                             uint32_t* __restrict__ wtab) {
   for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < n_words;
        w += (int64_t)gridDim.x * blockDim.x) {
     const u32x4* f = reinterpret_cast<const u32x4*>(flag + (w << 5));
@@ -120,23 +122,22 @@ __global__ void k_fold_flags(const uint8_t* __restrict__ flag, int64_t n_words,
       const uint32_t q = (x & 1u) | ((x >> 7) & 2u) | ((x >> 14) & 4u) | ((x >> 21) & 8u);
       m |= q << (4 * i);
     }
-    bitmap[w] = m;
+    wtab[2 * w] = m;
   }
 }
 
 struct PopcountIn {
-  const uint32_t* bitmap;
-  __device__ int64_t operator()(int64_t w) const { return __popc(bitmap[w]); }
+  const uint32_t* wtab;
+  __device__ int64_t operator()(int64_t w) const { return __popc(wtab[2 * w]); }
 };
 
 // Writes each word's packed offset and compacts its set bits, ascending.
 struct CompactOut {
-  const uint32_t* bitmap;
-  int32_t* word_off;
+  uint32_t* wtab;
   int32_t* unique_cols;
   __device__ void operator()(int64_t w, int64_t prefix, int64_t) const {
-    word_off[w] = (int32_t)prefix;
-    uint32_t bits = bitmap[w];
+    wtab[2 * w + 1] = (uint32_t)prefix;
+    uint32_t bits = wtab[2 * w];
     int32_t o = (int32_t)prefix;
     const int32_t base = (int32_t)(w << 5);
     while (bits) {
@@ -149,18 +150,18 @@ struct CompactOut {
 
 // colmap[k] = packed position of col[k] = offset of its word + set bits below it.
 __global__ void k_remap(const int32_t* __restrict__ col, int64_t nnz,
-                        const uint32_t* __restrict__ bitmap, const int32_t* __restrict__ word_off,
-                        int32_t* __restrict__ colmap) {
+                        const uint32_t* __restrict__ wtab, int32_t* __restrict__ colmap) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz;
        k += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t c = (uint32_t)col[k];
     const uint32_t below = (1u << (c & 31u)) - 1u;
-    colmap[k] = word_off[c >> 5] + __popc(bitmap[c >> 5] & below);
+    const u32x2 e = reinterpret_cast<const u32x2*>(wtab)[c >> 5];
+    colmap[k] = (int32_t)e.y + __popc(e.x & below);
   }
 }
 
 // block_off[q] = packed position of the first column id of block q.
-__global__ void k_block_off(const uint32_t* __restrict__ bitmap, const int32_t* __restrict__ word_off,
+__global__ void k_block_off(const uint32_t* __restrict__ wtab,
                             int64_t n_cols, int64_t K, int32_t P, const int64_t* __restrict__ d_U,
                             int64_t* __restrict__ block_off) {
   const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -171,7 +172,7 @@ __global__ void k_block_off(const uint32_t* __restrict__ bitmap, const int32_t* 
     return;
   }
   const uint32_t below = (1u << ((uint32_t)c0 & 31u)) - 1u;
-  block_off[q] = (int64_t)word_off[c0 >> 5] + __popc(bitmap[c0 >> 5] & below);
+  block_off[q] = (int64_t)wtab[2 * (c0 >> 5) + 1] + __popc(wtab[2 * (c0 >> 5)] & below);
 }
 
 unsigned grid_for(int64_t n, int64_t cap = 65536) {
@@ -229,17 +230,15 @@ int run_select(shiro_plan plan, hipStream_t s, bool sync) {
     k_mark<<<grid_for(nnz), kBlock, 0, s>>>(plan->col, nnz, plan->flags);
     SHIRO_LAUNCH_CHECK();
   }
-  k_fold_flags<<<grid_for(nw), kBlock, 0, s>>>(plan->flags, nw, plan->bitmap);
+  k_fold_flags<<<grid_for(nw), kBlock, 0, s>>>(plan->flags, nw, plan->wtab);
   SHIRO_LAUNCH_CHECK();
-  SHIRO_TRY(scan_generic<4>(PopcountIn{plan->bitmap}, nw,
-                         CompactOut{plan->bitmap, plan->word_off, plan->unique_cols}, d_U,
+  SHIRO_TRY(scan_generic<4>(PopcountIn{plan->wtab}, nw, CompactOut{plan->wtab, plan->unique_cols}, d_U,
                          scan_tmp, s));
   if (nnz > 0) {
-    k_remap<<<grid_for(nnz), kBlock, 0, s>>>(plan->col, nnz, plan->bitmap, plan->word_off,
-                                              plan->colmap);
+    k_remap<<<grid_for(nnz), kBlock, 0, s>>>(plan->col, nnz, plan->wtab, plan->colmap);
     SHIRO_LAUNCH_CHECK();
   }
-  k_block_off<<<grid_for(plan->P + 1), kBlock, 0, s>>>(plan->bitmap, plan->word_off, plan->n_cols,
+  k_block_off<<<grid_for(plan->P + 1), kBlock, 0, s>>>(plan->wtab, plan->n_cols,
                                                         plan->K, plan->P, d_U, plan->block_off);
   SHIRO_LAUNCH_CHECK();
   if (!sync) return SHIRO_OK;
