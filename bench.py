@@ -3,7 +3,8 @@
 
 A step is one pass of the whole path over the workload: select (the
 selection kernels, re-run on the device), pack_B, spmm (all column blocks in
-one launch) and spmm_backward (dBpacked, add-scatter into dB, dvals),
+one launch) and spmm_backward (the gradients autograd needs: A^T dY
+add-scattered into dB at the selected rows, and dvals),
 captured once in a HIP graph and replayed.  Inputs are resident in HBM
 before timing starts.  The metric counts 2*nnz*N flops for each of the three
 products of a step (Y, dBpacked, dvals).
@@ -122,7 +123,6 @@ def main():
     vals = A.vals
     Bp = torch.empty(U, N, dtype=tdt, device=dev)
     Y = torch.empty(M, N, dtype=tdt, device=dev)
-    dBp = torch.empty(U, N, dtype=tdt, device=dev)
     dB = torch.zeros(A.n_cols, N, dtype=tdt, device=dev)
     dvals = torch.zeros(A.nnz, dtype=torch.float32, device=dev)
 
@@ -130,7 +130,7 @@ def main():
         shiro.refresh_selection(plan)
         shiro.pack_B(plan, B, out=Bp)
         shiro.spmm(plan, vals, Bp, out=Y)
-        shiro.spmm_backward(plan, vals, G, Bp, dBpacked=dBp, dB=dB, dvals=dvals)
+        shiro.spmm_backward(plan, vals, G, Bp, dB=dB, dvals=dvals)
 
     # ---- capture one step as a HIP graph ----
     cs = torch.cuda.Stream()
@@ -169,15 +169,15 @@ def main():
         "select": 8 * nnz + 4 * U + 2 * ((A.n_cols + 7) // 8),
         "pack_B": 2 * U * N * sz,
         "spmm": 8 * (M + 1) + 8 * nnz + U * N * sz + M * N * sz,
-        # A^T dY -> dBpacked, add-scatter into dB, dvals, in one pass over the transposed pattern
-        "backward": 8 * (U + 1) + 8 * nnz + 4 * nnz + R_nonempty * N * sz + U * N * sz
-        + U * N * sz + 2 * U * N * sz,
+        # A^T dY add-scattered into dB (read + write of the U selected rows) and
+        # dvals, in one pass over the transposed pattern
+        "backward": 8 * (U + 1) + 8 * nnz + 4 * nnz + R_nonempty * N * sz + U * N * sz + 2 * U * N * sz,
     }
     ops = {
         "select": lambda: shiro.refresh_selection(plan),
         "pack_B": lambda: shiro.pack_B(plan, B, out=Bp),
         "spmm": lambda: shiro.spmm(plan, vals, Bp, out=Y),
-        "backward": lambda: shiro.spmm_backward(plan, vals, G, Bp, dBpacked=dBp, dB=dB, dvals=dvals),
+        "backward": lambda: shiro.spmm_backward(plan, vals, G, Bp, dB=dB, dvals=dvals),
     }
     reps = 10
     kern_us = {}
@@ -224,7 +224,7 @@ def main():
         "dtype": args.dtype,
         "data": "synthetic",
         "config": {"workload": args.workload, "n": A.n_rows, "P": A.P, "p": A.p, "rows": M, "nnz": nnz,
-                   "U": U, "N": N, "step": "select+pack_B+spmm+spmm_backward(dBpacked,dB,dvals)"},
+                   "U": U, "N": N, "step": "select+pack_B+spmm+spmm_backward(dB scatter, dvals)"},
         "roofline": roofline,
         "step_hbm_frac": round(alg_step / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "kernels_us": {k: round(v, 2) for k, v in kern_us.items()},
@@ -272,14 +272,13 @@ def main():
             shiro.prepare(plan, N, torch.bfloat16, ops=("spmm", "backward"))
             Bph = torch.empty(U, N, dtype=torch.bfloat16, device=dev)
             Yh = torch.empty(M, N, dtype=torch.bfloat16, device=dev)
-            dBph = torch.empty(U, N, dtype=torch.bfloat16, device=dev)
             dBh = torch.zeros(A.n_cols, N, dtype=torch.bfloat16, device=dev)
 
             def step_bf16():
                 shiro.refresh_selection(plan)
                 shiro.pack_B(plan, Bh, out=Bph)
                 shiro.spmm(plan, vals, Bph, out=Yh)
-                shiro.spmm_backward(plan, vals, Gh, Bph, dBpacked=dBph, dB=dBh, dvals=dvals)
+                shiro.spmm_backward(plan, vals, Gh, Bph, dB=dBh, dvals=dvals)
 
             if not args.no_autotune:
                 shiro.autotune(plan, N, torch.bfloat16, ops=("spmm", "backward"))
@@ -289,10 +288,9 @@ def main():
             out["bf16_kernels_us"] = {
                 "pack_B": round(timed(lambda: shiro.pack_B(plan, Bh, out=Bph)), 2),
                 "spmm": round(timed(lambda: shiro.spmm(plan, vals, Bph, out=Yh)), 2),
-                "backward": round(timed(lambda: shiro.spmm_backward(plan, vals, Gh, Bph, dBpacked=dBph, dB=dBh,
-                                                                    dvals=dvals)), 2),
+                "backward": round(timed(lambda: shiro.spmm_backward(plan, vals, Gh, Bph, dB=dBh, dvals=dvals)), 2),
             }
-            del Bh, Gh, Bph, Yh, dBph, dBh
+            del Bh, Gh, Bph, Yh, dBh
         # sampled parity of Y at full size against the FP64 oracle
         import oracle
 

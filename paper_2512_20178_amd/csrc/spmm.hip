@@ -197,25 +197,38 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) d[e] = cvalid ? d[e] : 0.f;
       }
-      for (int64_t k = kb; k < ke; k += STEP) {
-        // Every slot loads (idle slots re-read the row's last nonzero, a
-        // cache hit) so the loads of all slots are in flight together; the
-        // accumulation of idle slots is masked by a select.
-        int32_t xi[UNROLL];
-        float v[UNROLL];
-        bool ok[UNROLL];
+      // Software pipeline: the index/value loads of the next step are
+      // issued while the current step's row gathers are in flight, so each
+      // step waits for one memory round trip instead of two.  Every slot
+      // loads (idle slots re-read the row's last nonzero, a cache hit) and
+      // idle slots are masked by a select, not a branch.
+      int32_t xi[UNROLL];
+      float v[UNROLL];
+      bool ok[UNROLL];
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-          const int64_t kk = k + u * G + g;
-          ok[u] = kk < ke;
-          const int64_t kc = ok[u] ? kk : ke - 1;
-          xi[u] = idx[kc];
-          v[u] = vals[kc];
-        }
+      for (int u = 0; u < UNROLL; ++u) {
+        const int64_t kk = kb + u * G + g;
+        ok[u] = kk < ke;
+        const int64_t kc = ok[u] ? kk : ke - 1;
+        xi[u] = idx[kc];
+        v[u] = vals[kc];
+      }
+      for (int64_t k = kb; k < ke; k += STEP) {
         float x[UNROLL][VEC];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
           Elem<TIN>::template load<VEC>(X + (int64_t)xi[u] * ldx + cl, x[u]);
+        int32_t xin[UNROLL];
+        float vn[UNROLL];
+        bool okn[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          const int64_t kk = k + STEP + u * G + g;
+          okn[u] = kk < ke;
+          const int64_t kc = okn[u] ? kk : ke - 1;
+          xin[u] = idx[kc];
+          vn[u] = vals[kc];
+        }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
 #pragma unroll
@@ -233,6 +246,12 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
             for (int sft = 1; sft < LANES; sft <<= 1) q += __shfl_xor(q, sft, kWave);
             if (li == 0 && ok[u]) dot_out[k + u * G + g] = q;
           }
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          xi[u] = xin[u];
+          v[u] = vn[u];
+          ok[u] = okn[u];
         }
       }
       // combine the lane groups (fixed butterfly order)
