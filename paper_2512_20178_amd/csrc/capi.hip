@@ -249,30 +249,30 @@ static void cache_store(const std::string& key, const shiro_tuning_t& t) {
     << t.xcd_remap << ' ' << t.wg_per_cu << '\n';
 }
 
+// Median of 9 timed runs after one warm-up (the warm-up also builds any
+// work list the candidate needs).
 template <class F>
 static int time_candidate(hipStream_t s, F&& run, float* ms_out) {
-  hipEvent_t e0, e1;
-  SHIRO_HIP(hipEventCreate(&e0));
-  SHIRO_HIP(hipEventCreate(&e1));
-  int rc = run();  // warm-up (also builds work lists)
-  if (rc != SHIRO_OK) {
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    return rc;
+  constexpr int kReps = 9;
+  hipEvent_t ev[kReps + 1];
+  for (auto& e : ev) SHIRO_HIP(hipEventCreate(&e));
+  int rc = run();
+  if (rc == SHIRO_OK) {
+    (void)hipEventRecord(ev[0], s);
+    for (int rep = 0; rep < kReps && rc == SHIRO_OK; ++rep) {
+      rc = run();
+      (void)hipEventRecord(ev[rep + 1], s);
+    }
+    (void)hipEventSynchronize(ev[kReps]);
   }
-  float best = 1e30f;
-  for (int rep = 0; rep < 5 && rc == SHIRO_OK; ++rep) {
-    (void)hipEventRecord(e0, s);
-    rc = run();
-    (void)hipEventRecord(e1, s);
-    (void)hipEventSynchronize(e1);
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    best = std::min(best, ms);
+  float t[kReps];
+  for (int rep = 0; rep < kReps; ++rep) {
+    t[rep] = 0.f;
+    (void)hipEventElapsedTime(&t[rep], ev[rep], ev[rep + 1]);
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  *ms_out = best;
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  std::sort(t, t + kReps);
+  *ms_out = t[kReps / 2];
   return rc;
 }
 

@@ -182,12 +182,30 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
   for (int32_t w = w_begin; w < w_end; ++w) {
     const int32_t i0 = chunk_row[w], i1 = chunk_row[w + 1];
     const int64_t j0 = chunk_nz[w], j1 = chunk_nz[w + 1];
-    int64_t rs = i0 < R ? ptr[i0] : 0;
+    if (i0 >= R) continue;
+    int64_t rs = ptr[i0], re = ptr[i0 + 1];
+    // Indices and values of a row's first step, prefetched during the last
+    // step of the previous row (so short rows do not wait for them).
+    int32_t xi[UNROLL];
+    float v[UNROLL];
+    bool ok[UNROLL];
+    bool have = false;
     for (int32_t r = i0; r <= i1 && r < R; ++r) {
-      const int64_t re = ptr[r + 1];
       if (r == i1 && j1 <= rs) break;  // chunk holds nothing of row i1
       const int64_t kb = rs > j0 ? rs : j0;
       const int64_t ke = re < j1 ? re : j1;
+      const bool head = (r == i0) && (j0 > rs);
+      const bool tail = (r == i1);
+      const bool complete = !head && !tail;
+      // the next row of the chunk starts where this one ends
+      const bool has_next = (r + 1 <= i1) && (r + 1 < R);
+      const int64_t re2 = has_next ? ptr[r + 2] : re;
+      const int64_t ke2 = re2 < j1 ? re2 : j1;
+      const bool next_nonempty = has_next && ke2 > re;
+      // the add-scatter target is read now so its latency hides behind the gathers
+      float pre[VEC];
+      if (scat && complete && g == 0 && cvalid)
+        Elem<TOUT>::template load<VEC>(scat + (int64_t)scat_idx[r] * lds + c, pre);
       float acc[VEC];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
@@ -197,22 +215,21 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) d[e] = cvalid ? d[e] : 0.f;
       }
-      // Software pipeline: the index/value loads of the next step are
-      // issued while the current step's row gathers are in flight, so each
-      // step waits for one memory round trip instead of two.  Every slot
-      // loads (idle slots re-read the row's last nonzero, a cache hit) and
-      // idle slots are masked by a select, not a branch.
-      int32_t xi[UNROLL];
-      float v[UNROLL];
-      bool ok[UNROLL];
+      if (!have && kb < ke) {
 #pragma unroll
-      for (int u = 0; u < UNROLL; ++u) {
-        const int64_t kk = kb + u * G + g;
-        ok[u] = kk < ke;
-        const int64_t kc = ok[u] ? kk : ke - 1;
-        xi[u] = idx[kc];
-        v[u] = vals[kc];
+        for (int u = 0; u < UNROLL; ++u) {
+          const int64_t kk = kb + u * G + g;
+          ok[u] = kk < ke;
+          const int64_t kc = ok[u] ? kk : ke - 1;
+          xi[u] = idx[kc];
+          v[u] = vals[kc];
+        }
       }
+      have = false;
+      // Software pipeline: the index/value loads of the next step (or of the
+      // next row's first step) are issued while this step's row gathers are
+      // in flight.  Every slot loads (idle slots re-read a valid nonzero, a
+      // cache hit) and idle slots are masked by a select, not a branch.
       for (int64_t k = kb; k < ke; k += STEP) {
         float x[UNROLL][VEC];
 #pragma unroll
@@ -221,13 +238,26 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
         int32_t xin[UNROLL];
         float vn[UNROLL];
         bool okn[UNROLL];
+        const bool same_row = k + STEP < ke;
+        const int64_t nb = same_row ? k + STEP : re;
+        const int64_t nl = same_row ? ke : ke2;
+        if (same_row || next_nonempty) {
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-          const int64_t kk = k + STEP + u * G + g;
-          okn[u] = kk < ke;
-          const int64_t kc = okn[u] ? kk : ke - 1;
-          xin[u] = idx[kc];
-          vn[u] = vals[kc];
+          for (int u = 0; u < UNROLL; ++u) {
+            const int64_t kk = nb + u * G + g;
+            okn[u] = kk < nl;
+            const int64_t kc = okn[u] ? kk : nl - 1;
+            xin[u] = idx[kc];
+            vn[u] = vals[kc];
+          }
+          have = !same_row;
+        } else {
+#pragma unroll
+          for (int u = 0; u < UNROLL; ++u) {
+            xin[u] = xi[u];
+            vn[u] = 0.f;
+            okn[u] = false;
+          }
         }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
@@ -259,17 +289,21 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
       for (int sft = LANES; sft < kWave; sft <<= 1)
 #pragma unroll
         for (int e = 0; e < VEC; ++e) acc[e] += __shfl_xor(acc[e], sft, kWave);
-      const bool head = (r == i0) && (j0 > rs);
-      const bool tail = (r == i1);
       if (g == 0 && cvalid) {
-        if (!head && !tail) {
-          epilogue_row<TOUT, VEC>(out, ldo, scat, lds, scat_idx, r, c, acc);
+        if (complete) {
+          if (out) Elem<TOUT>::template store<VEC>(out + (int64_t)r * ldo + c, acc);
+          if (scat) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) pre[e] += acc[e];
+            Elem<TOUT>::template store<VEC>(scat + (int64_t)scat_idx[r] * lds + c, pre);
+          }
         } else {
           float* cs = carry + ((int64_t)w * 2 + (head ? 0 : 1)) * N + c;
           Elem<float>::template store<VEC>(cs, acc);
         }
       }
       rs = re;
+      re = re2;
     }
   }
 }
