@@ -76,6 +76,49 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float x) {
   return __builtin_bit_cast(uint16_t, b);
 }
 
+// ---------------------------------------------------------------------------
+// cross-lane sums without the LDS crossbar (DPP row ops, permlane swaps)
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float x) {
+  return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, false));
+}
+
+// Sum of x over each aligned group of LANES lanes.  The sum is exact in the
+// group's last lane (lane LANES-1 of the group); other lanes hold partial
+// sums.  Every step adds two disjoint partial sums, so the result does not
+// depend on anything but the inputs.
+template <int LANES>
+__device__ __forceinline__ float group_sum(float x) {
+  static_assert(LANES == 8 || LANES == 16 || LANES == 32 || LANES == 64, "lanes");
+  x = dpp_add<0xB1, 0xF>(x);   // quad_perm [1,0,3,2]
+  x = dpp_add<0x4E, 0xF>(x);   // quad_perm [2,3,0,1]
+  x = dpp_add<0x141, 0xF>(x);  // row_half_mirror: 8-lane sums
+  if constexpr (LANES >= 16) x = dpp_add<0x140, 0xF>(x);  // row_mirror: 16-lane sums
+  if constexpr (LANES >= 32) x = dpp_add<0x142, 0xA>(x);  // row_bcast15 into rows 1, 3
+  if constexpr (LANES >= 64) x = dpp_add<0x143, 0xC>(x);  // row_bcast31 into rows 2, 3
+  return x;
+}
+
+// Lane-wise sum over the 64/LANES groups of a wavefront (lane l gets
+// sum over g of x[l mod LANES + g LANES]), in a fixed pairing order.
+template <int LANES>
+__device__ __forceinline__ float groups_sum(float x) {
+  if constexpr (LANES <= 8) {
+    // pair lanes i and i+8 inside each row of 16 (rotate by 8)
+    x = x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xF, 0xF, false));
+  }
+  if constexpr (LANES <= 16) {
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(x), __float_as_int(x), false, false);
+    x = __int_as_float(r[0]) + __int_as_float(r[1]);
+  }
+  if constexpr (LANES <= 32) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(x), __float_as_int(x), false, false);
+    x = __int_as_float(r[0]) + __int_as_float(r[1]);
+  }
+  return x;
+}
+
 // Element traits: VEC elements of T per lane, converted to float.
 template <typename T>
 struct Elem;

@@ -164,7 +164,7 @@ __device__ __forceinline__ int32_t logical_block(int32_t remap) {
 // pattern row's own dense row D[r]: in the transposed product this is the
 // gradient of the values, dvals = dY[row] . Bpacked[u], computed from the
 // same dY gathers (no second pass over the nonzeros).
-template <typename TIN, typename TOUT, int LANES, int VEC, int UNROLL, bool DOT>
+template <typename TIN, typename TOUT, int LANES, int VEC, int UNROLL, bool DOT, bool SCAT>
 __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
   constexpr int G = kWave / LANES;
   constexpr int STEP = G * UNROLL;
@@ -184,6 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
     const int64_t j0 = chunk_nz[w], j1 = chunk_nz[w + 1];
     if (i0 >= R) continue;
     int64_t rs = ptr[i0], re = ptr[i0 + 1];
+    int32_t sidx = SCAT ? scat_idx[i0] : 0;
     // Indices and values of a row's first step, prefetched during the last
     // step of the previous row (so short rows do not wait for them).
     int32_t xi[UNROLL];
@@ -200,12 +201,14 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
       // the next row of the chunk starts where this one ends
       const bool has_next = (r + 1 <= i1) && (r + 1 < R);
       const int64_t re2 = has_next ? ptr[r + 2] : re;
+      const int32_t sidx2 = (SCAT && has_next) ? scat_idx[r + 1] : 0;
       const int64_t ke2 = re2 < j1 ? re2 : j1;
       const bool next_nonempty = has_next && ke2 > re;
       // the add-scatter target is read now so its latency hides behind the gathers
       float pre[VEC];
-      if (scat && complete && g == 0 && cvalid)
-        Elem<TOUT>::template load<VEC>(scat + (int64_t)scat_idx[r] * lds + c, pre);
+      if constexpr (SCAT) {
+        if (complete) Elem<TOUT>::template load<VEC>(scat + (int64_t)sidx * lds + cl, pre);
+      }
       float acc[VEC];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
@@ -228,37 +231,30 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
       have = false;
       // Software pipeline: the index/value loads of the next step (or of the
       // next row's first step) are issued while this step's row gathers are
-      // in flight.  Every slot loads (idle slots re-read a valid nonzero, a
-      // cache hit) and idle slots are masked by a select, not a branch.
+      // in flight.  All loads are unconditional (idle slots re-read a valid
+      // nonzero, a cache hit) so the compiler can count outstanding loads
+      // instead of draining them; idle slots are masked by selects.
       for (int64_t k = kb; k < ke; k += STEP) {
         float x[UNROLL][VEC];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
           Elem<TIN>::template load<VEC>(X + (int64_t)xi[u] * ldx + cl, x[u]);
+        const bool same_row = k + STEP < ke;
+        const bool pf = same_row || next_nonempty;
+        const int64_t nb = same_row ? k + STEP : (next_nonempty ? re : kb);
+        const int64_t nl = same_row ? ke : (next_nonempty ? ke2 : ke);
         int32_t xin[UNROLL];
         float vn[UNROLL];
         bool okn[UNROLL];
-        const bool same_row = k + STEP < ke;
-        const int64_t nb = same_row ? k + STEP : re;
-        const int64_t nl = same_row ? ke : ke2;
-        if (same_row || next_nonempty) {
 #pragma unroll
-          for (int u = 0; u < UNROLL; ++u) {
-            const int64_t kk = nb + u * G + g;
-            okn[u] = kk < nl;
-            const int64_t kc = okn[u] ? kk : nl - 1;
-            xin[u] = idx[kc];
-            vn[u] = vals[kc];
-          }
-          have = !same_row;
-        } else {
-#pragma unroll
-          for (int u = 0; u < UNROLL; ++u) {
-            xin[u] = xi[u];
-            vn[u] = 0.f;
-            okn[u] = false;
-          }
+        for (int u = 0; u < UNROLL; ++u) {
+          const int64_t kk = nb + u * G + g;
+          okn[u] = pf && kk < nl;
+          const int64_t kc = kk < nl ? kk : nl - 1;
+          xin[u] = idx[kc];
+          vn[u] = vals[kc];
         }
+        have = !same_row && next_nonempty;
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
 #pragma unroll
@@ -272,9 +268,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
             float q = 0.f;
 #pragma unroll
             for (int e = 0; e < VEC; ++e) q = fmaf(d[e], x[u][e], q);
-#pragma unroll
-            for (int sft = 1; sft < LANES; sft <<= 1) q += __shfl_xor(q, sft, kWave);
-            if (li == 0 && ok[u]) dot_out[k + u * G + g] = q;
+            q = group_sum<LANES>(q);
+            if (li == LANES - 1 && ok[u]) dot_out[k + u * G + g] = q;
           }
         }
 #pragma unroll
@@ -284,18 +279,16 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
           ok[u] = okn[u];
         }
       }
-      // combine the lane groups (fixed butterfly order)
+      // combine the lane groups (fixed pairing order)
 #pragma unroll
-      for (int sft = LANES; sft < kWave; sft <<= 1)
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[e] += __shfl_xor(acc[e], sft, kWave);
+      for (int e = 0; e < VEC; ++e) acc[e] = groups_sum<LANES>(acc[e]);
       if (g == 0 && cvalid) {
         if (complete) {
           if (out) Elem<TOUT>::template store<VEC>(out + (int64_t)r * ldo + c, acc);
-          if (scat) {
+          if constexpr (SCAT) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) pre[e] += acc[e];
-            Elem<TOUT>::template store<VEC>(scat + (int64_t)scat_idx[r] * lds + c, pre);
+            Elem<TOUT>::template store<VEC>(scat + (int64_t)sidx * lds + c, pre);
           }
         } else {
           float* cs = carry + ((int64_t)w * 2 + (head ? 0 : 1)) * N + c;
@@ -304,6 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
       }
       rs = re;
       re = re2;
+      sidx = sidx2;
     }
   }
 }
@@ -439,10 +433,9 @@ __global__ __launch_bounds__(kBlock) void k_sddmm(
         }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-#pragma unroll
-          for (int sft = 1; sft < LANES; sft <<= 1) part[u] += __shfl_xor(part[u], sft, kWave);
+          part[u] = group_sum<LANES>(part[u]);
           const int64_t kk = k + u * G + g;
-          if (li == 0 && kk < ke) dvals[kk] = part[u];
+          if (li == LANES - 1 && kk < ke) dvals[kk] = part[u];
         }
       }
     }
@@ -676,13 +669,13 @@ int grid_waves(shiro_plan plan, const shiro_tuning_t& t, int32_t W, int32_t* chu
   return SHIRO_OK;
 }
 
-template <typename TIN, typename TOUT, int VEC, bool DOT>
+template <typename TIN, typename TOUT, int VEC, bool DOT, bool SCAT>
 int spmm_dispatch(const shiro_tuning_t& t, dim3 grid, hipStream_t s, const SpmmArgs& a) {
-#define SHIRO_SPMM_CASE(L, U)                                                               \
-  if (t.lanes == L && t.unroll == U) {                                                      \
-    k_spmm<TIN, TOUT, L, VEC, U, DOT><<<grid, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a)); \
-    SHIRO_LAUNCH_CHECK();                                                                   \
-    return SHIRO_OK;                                                                        \
+#define SHIRO_SPMM_CASE(L, U)                                                                      \
+  if (t.lanes == L && t.unroll == U) {                                                             \
+    k_spmm<TIN, TOUT, L, VEC, U, DOT, SCAT><<<grid, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a)); \
+    SHIRO_LAUNCH_CHECK();                                                                          \
+    return SHIRO_OK;                                                                               \
   }
   SHIRO_SPMM_CASE(8, 1) SHIRO_SPMM_CASE(8, 2) SHIRO_SPMM_CASE(8, 4)
   SHIRO_SPMM_CASE(16, 1) SHIRO_SPMM_CASE(16, 2) SHIRO_SPMM_CASE(16, 4)
@@ -731,11 +724,19 @@ int run_spmm_family(shiro_plan plan, shiro_tuning_t t, const WorkList* wl, SpmmA
   constexpr int V16 = Elem<TIN>::kVec16;
   if (a.dot_out) {
     if (ntiles != 1) return set_error(SHIRO_ERR_UNSUPPORTED, "fused dvals needs one column tile");
-    if (vec == V16) SHIRO_TRY((spmm_dispatch<TIN, TOUT, V16, true>(t, grid, s, a)));
-    else SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1, true>(t, grid, s, a)));
+    if (a.scat) {
+      if (vec == V16) SHIRO_TRY((spmm_dispatch<TIN, TOUT, V16, true, true>(t, grid, s, a)));
+      else SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1, true, true>(t, grid, s, a)));
+    } else {
+      if (vec == V16) SHIRO_TRY((spmm_dispatch<TIN, TOUT, V16, true, false>(t, grid, s, a)));
+      else SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1, true, false>(t, grid, s, a)));
+    }
+  } else if (a.scat) {
+    if (vec == V16) SHIRO_TRY((spmm_dispatch<TIN, TOUT, V16, false, true>(t, grid, s, a)));
+    else SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1, false, true>(t, grid, s, a)));
   } else {
-    if (vec == V16) SHIRO_TRY((spmm_dispatch<TIN, TOUT, V16, false>(t, grid, s, a)));
-    else SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1, false>(t, grid, s, a)));
+    if (vec == V16) SHIRO_TRY((spmm_dispatch<TIN, TOUT, V16, false, false>(t, grid, s, a)));
+    else SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1, false, false>(t, grid, s, a)));
   }
   if (wl->nsplit == 0) return SHIRO_OK;
   const unsigned fb = (unsigned)std::min<int64_t>(wl->nsplit, 65536);
