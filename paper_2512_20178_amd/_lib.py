@@ -95,7 +95,7 @@ class Tuning(ctypes.Structure):
         ("chunk", ctypes.c_int32),
         ("lanes", ctypes.c_int32),
         ("unroll", ctypes.c_int32),
-        ("hot_rows", ctypes.c_int32),
+        ("group_rows", ctypes.c_int32),
         ("xcd_remap", ctypes.c_int32),
         ("wg_per_cu", ctypes.c_int32),
     ]

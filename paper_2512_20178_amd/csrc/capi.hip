@@ -118,14 +118,17 @@ int ensure_tvals(shiro_plan plan, bool allocate) {
   return SHIRO_OK;
 }
 
+// Defaults from a sweep on MI355X (panel of a 2^24 R-MAT, N = 128): small
+// chunks, one nonzero in flight per lane group (high occupancy wins for
+// these gather-bound loops), 8 workgroups per CU.
 shiro_tuning_t default_tuning(int kernel, int32_t, shiro_dtype) {
   shiro_tuning_t t;
-  t.chunk = kernel == SHIRO_KERNEL_SDDMM ? 512 : 256;
+  t.chunk = 128;
   t.lanes = 64;
-  t.unroll = 2;
-  t.hot_rows = 0;
+  t.unroll = kernel == SHIRO_KERNEL_SPMM ? 1 : 2;
+  t.group_rows = 0;
   t.xcd_remap = 0;
-  t.wg_per_cu = 8;
+  t.wg_per_cu = kernel == SHIRO_KERNEL_SPMM_T ? 16 : 8;
   return t;
 }
 
@@ -136,7 +139,7 @@ int validate_tuning(int kernel, int32_t, shiro_dtype, const shiro_tuning_t& t) {
     return set_error(SHIRO_ERR_INVALID_ARG, "tuning: lanes must be 8, 16, 32 or 64");
   if (t.unroll != 1 && t.unroll != 2 && t.unroll != 4)
     return set_error(SHIRO_ERR_INVALID_ARG, "tuning: unroll must be 1, 2 or 4");
-  if (t.hot_rows != 0) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: hot_rows must be 0 in this build");
+  if (t.group_rows != 0 && t.group_rows != 1) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: group_rows must be 0 or 1");
   if (t.xcd_remap != 0 && t.xcd_remap != 1) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: xcd_remap must be 0 or 1");
   if (t.wg_per_cu < 1 || t.wg_per_cu > 32) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: wg_per_cu outside [1, 32]");
   return SHIRO_OK;
@@ -231,7 +234,7 @@ static bool cache_lookup(const std::string& key, shiro_tuning_t* t) {
     std::istringstream is(line);
     std::string k;
     shiro_tuning_t c;
-    if (is >> k >> c.chunk >> c.lanes >> c.unroll >> c.hot_rows >> c.xcd_remap >> c.wg_per_cu) {
+    if (is >> k >> c.chunk >> c.lanes >> c.unroll >> c.group_rows >> c.xcd_remap >> c.wg_per_cu) {
       if (k == key) {
         *t = c;
         found = true;  // last entry wins
@@ -245,7 +248,7 @@ static void cache_store(const std::string& key, const shiro_tuning_t& t) {
   const char* path = std::getenv("SHIRO_TUNE_CACHE");
   if (!path || !*path) return;
   std::ofstream f(path, std::ios::app);
-  f << key << ' ' << t.chunk << ' ' << t.lanes << ' ' << t.unroll << ' ' << t.hot_rows << ' '
+  f << key << ' ' << t.chunk << ' ' << t.lanes << ' ' << t.unroll << ' ' << t.group_rows << ' '
     << t.xcd_remap << ' ' << t.wg_per_cu << '\n';
 }
 
@@ -314,15 +317,26 @@ static int tune_one(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt, Tune
     }
   // stage 2: lane width, occupancy, XCD placement around the best
   const shiro_tuning_t base = best;
-  for (int lanes : {64, 32, 16})
-    for (int wg : {4, 8, 16})
-      for (int xcd : {0, 1}) {
-        shiro_tuning_t t = base;
-        t.lanes = lanes;
-        t.wg_per_cu = wg;
-        t.xcd_remap = xcd;
-        SHIRO_TRY(consider(t));
-      }
+  for (int grp : {0, 1})
+    for (int lanes : {64, 32, 16})
+      for (int wg : {4, 8, 16})
+        for (int xcd : {0, 1}) {
+          shiro_tuning_t t = base;
+          t.group_rows = grp;
+          t.lanes = lanes;
+          t.wg_per_cu = wg;
+          t.xcd_remap = xcd;
+          SHIRO_TRY(consider(t));
+        }
+  // stage 3: work size and depth again around the best layout
+  const shiro_tuning_t base3 = best;
+  for (int chunk : {64, 128, 256, 512})
+    for (int unroll : {1, 2, 4}) {
+      shiro_tuning_t t = base3;
+      t.chunk = chunk;
+      t.unroll = unroll;
+      SHIRO_TRY(consider(t));
+    }
   plan->tuning[TuneKey{kernel, N, (int)dt}] = best;
   cache_store(key, best);
   return SHIRO_OK;

@@ -302,6 +302,100 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
   }
 }
 
+// Variant for short rows: lane group g of a wavefront takes rows i0+g,
+// i0+g+G, ... of the chunk, one nonzero per slot, so a wavefront advances G
+// rows at once instead of one.  Row bookkeeping is per group (vector
+// registers); groups diverge only in their trip counts.  The order of the
+// sums inside a row is fixed by the row, so results stay reproducible.
+template <typename TIN, typename TOUT, int LANES, int VEC, int UNROLL, bool DOT, bool SCAT>
+__global__ __launch_bounds__(kBlock) void k_spmm_grp(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
+  constexpr int G = kWave / LANES;
+  const int lane = lane_id();
+  const int g = lane / LANES;
+  const int li = lane % LANES;
+  const int64_t c = (int64_t)blockIdx.y * (LANES * VEC) + (int64_t)li * VEC;
+  const bool cvalid = c < N;
+  const int64_t cl = cvalid ? c : 0;
+
+  const int32_t gw = uniform(logical_block(xcd_remap) * kWavesPerBlock + wave_id());
+  const int32_t w_begin = gw * cpw;
+  const int32_t w_end = min(w_begin + cpw, W);
+
+  for (int32_t w = w_begin; w < w_end; ++w) {
+    const int32_t i0 = chunk_row[w], i1 = chunk_row[w + 1];
+    const int64_t j0 = chunk_nz[w], j1 = chunk_nz[w + 1];
+    for (int32_t r = i0 + g; r <= i1 && r < R; r += G) {
+      const int64_t rs = ptr[r], re = ptr[r + 1];
+      if (r == i1 && j1 <= rs) break;  // chunk holds nothing of row i1
+      const int64_t kb = rs > j0 ? rs : j0;
+      const int64_t ke = re < j1 ? re : j1;
+      const bool head = (r == i0) && (j0 > rs);
+      const bool tail = (r == i1);
+      const bool complete = !head && !tail;
+      float pre[VEC];
+      if constexpr (SCAT) {
+        if (complete) Elem<TOUT>::template load<VEC>(scat + (int64_t)scat_idx[r] * lds + cl, pre);
+      }
+      float d[VEC];
+      if constexpr (DOT) {
+        Elem<TIN>::template load<VEC>(D + (int64_t)r * ldd + cl, d);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) d[e] = cvalid ? d[e] : 0.f;
+      }
+      float acc[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
+      for (int64_t k = kb; k < ke; k += UNROLL) {
+        int32_t xi[UNROLL];
+        float v[UNROLL];
+        bool ok[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          const int64_t kk = k + u;
+          ok[u] = kk < ke;
+          const int64_t kc = ok[u] ? kk : ke - 1;
+          xi[u] = idx[kc];
+          v[u] = vals[kc];
+        }
+        float x[UNROLL][VEC];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+          Elem<TIN>::template load<VEC>(X + (int64_t)xi[u] * ldx + cl, x[u]);
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) {
+            const float t = fmaf(v[u], x[u][e], acc[e]);
+            acc[e] = ok[u] ? t : acc[e];
+          }
+        if constexpr (DOT) {
+#pragma unroll
+          for (int u = 0; u < UNROLL; ++u) {
+            float q = 0.f;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) q = fmaf(d[e], x[u][e], q);
+            q = group_sum<LANES>(q);
+            if (li == LANES - 1 && ok[u]) dot_out[k + u] = q;
+          }
+        }
+      }
+      if (cvalid) {
+        if (complete) {
+          if (out) Elem<TOUT>::template store<VEC>(out + (int64_t)r * ldo + c, acc);
+          if constexpr (SCAT) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) pre[e] += acc[e];
+            Elem<TOUT>::template store<VEC>(scat + (int64_t)scat_idx[r] * lds + c, pre);
+          }
+        } else {
+          float* cs = carry + ((int64_t)w * 2 + (head ? 0 : 1)) * N + c;
+          Elem<float>::template store<VEC>(cs, acc);
+        }
+      }
+    }
+  }
+}
+
 // Rows cut by chunk boundaries.  split[3 i] = first chunk ws, split[3 i + 1]
 // = last chunk we, split[3 i + 2] = row r.  The row's pieces are the tail
 // slot of ws and the head slots of ws+1 .. we.  One workgroup per row:
@@ -671,11 +765,14 @@ int grid_waves(shiro_plan plan, const shiro_tuning_t& t, int32_t W, int32_t* chu
 
 template <typename TIN, typename TOUT, int VEC, bool DOT, bool SCAT>
 int spmm_dispatch(const shiro_tuning_t& t, dim3 grid, hipStream_t s, const SpmmArgs& a) {
-#define SHIRO_SPMM_CASE(L, U)                                                                      \
-  if (t.lanes == L && t.unroll == U) {                                                             \
-    k_spmm<TIN, TOUT, L, VEC, U, DOT, SCAT><<<grid, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a)); \
-    SHIRO_LAUNCH_CHECK();                                                                          \
-    return SHIRO_OK;                                                                               \
+#define SHIRO_SPMM_CASE(L, U)                                                                          \
+  if (t.lanes == L && t.unroll == U) {                                                                 \
+    if (t.group_rows)                                                                                  \
+      k_spmm_grp<TIN, TOUT, L, VEC, U, DOT, SCAT><<<grid, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a)); \
+    else                                                                                               \
+      k_spmm<TIN, TOUT, L, VEC, U, DOT, SCAT><<<grid, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a));     \
+    SHIRO_LAUNCH_CHECK();                                                                              \
+    return SHIRO_OK;                                                                                   \
   }
   SHIRO_SPMM_CASE(8, 1) SHIRO_SPMM_CASE(8, 2) SHIRO_SPMM_CASE(8, 4)
   SHIRO_SPMM_CASE(16, 1) SHIRO_SPMM_CASE(16, 2) SHIRO_SPMM_CASE(16, 4)
@@ -1030,7 +1127,7 @@ int launch_spmm_t(shiro_plan plan, const shiro_tuning_t& t, const float* vals, c
   const bool fuse = dvals && Bp && (int64_t)effective_lanes(64, N, v) * v >= N;
   if (fuse) {
     shiro_tuning_t tt = t;
-    tt.lanes = 64;  // one tile
+    tt.lanes = 64;  // one tile (effective lanes then cover N)
     a.D = Bp;
     a.ldd = ldp;
     a.dot_out = plan->tdvals;

@@ -97,5 +97,5 @@ def test_null_plan_errors(lib):
 def test_tuning_validation(lib):
     from paper_2512_20178_amd import _lib
 
-    t = _lib.Tuning(chunk=256, lanes=64, unroll=2, hot_rows=0, xcd_remap=0, wg_per_cu=8)
+    t = _lib.Tuning(chunk=256, lanes=64, unroll=2, group_rows=0, xcd_remap=0, wg_per_cu=8)
     assert lib.shiro_set_tuning(ctypes.c_void_p(None), 0, 128, 0, ctypes.byref(t)) == -1

@@ -233,6 +233,9 @@ def test_backward_bf16(shiro, run):
     dict(chunk=64, lanes=64, unroll=4),
     dict(chunk=1024, lanes=16, unroll=2, xcd_remap=1, wg_per_cu=2),
     dict(chunk=4096, lanes=32, unroll=4, wg_per_cu=1),
+    dict(chunk=16, lanes=32, unroll=1, group_rows=1),
+    dict(chunk=64, lanes=16, unroll=2, group_rows=1, xcd_remap=1),
+    dict(chunk=512, lanes=8, unroll=4, group_rows=1),
 ])
 def test_tunings_all_correct(shiro, run, knobs):
     """Small chunks split rows over many wavefronts (carry + fix-up path)."""
@@ -252,7 +255,7 @@ def test_tunings_all_correct(shiro, run, knobs):
     assert oracle.rel_err(gv, rdv, rdv_den) <= TOL_F32
     for k in ("spmm", "spmm_t", "sddmm"):  # back to the defaults for other tests
         shiro.set_tuning(run.plan, k, run.N, torch.float32, chunk=256 if k != "sddmm" else 512, lanes=64,
-                         unroll=2, xcd_remap=0, wg_per_cu=8)
+                         unroll=2, xcd_remap=0, wg_per_cu=8, group_rows=0)
 
 
 def test_graph_replays_match_eager(shiro):
