@@ -233,9 +233,12 @@ SHIRO_API int shiro_prepare(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t
                             shiro_stream_t stream);
 
 /* Time candidate tunings of the kernels in `ops` on scratch data of the
- * plan's shape at width N and keep the fastest per kernel in the plan.  If
- * the environment variable SHIRO_TUNE_CACHE names a file, results are read
- * from and appended to it (one line per key).  Allocates and synchronises. */
+ * plan's shape at width N and keep the fastest per kernel in the plan (the
+ * median of nine runs ranks each candidate).  The backward is tuned in the
+ * form autograd uses (dB add-scatter plus dvals), on a scratch dB of
+ * n_cols x N.  If the environment variable SHIRO_TUNE_CACHE names a file,
+ * results are read from it (no timing for keys it holds) and new results are
+ * appended (one line per key).  Allocates and synchronises. */
 SHIRO_API int shiro_autotune(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t ops,
                              shiro_stream_t stream);
 

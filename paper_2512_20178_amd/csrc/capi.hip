@@ -200,6 +200,7 @@ struct TuneBuffers {
   void* Y = nullptr;
   void* dY = nullptr;
   void* dBp = nullptr;
+  void* dB = nullptr;
   float* vals = nullptr;
   float* dvals = nullptr;
   ~TuneBuffers() {
@@ -207,6 +208,7 @@ struct TuneBuffers {
     dev_free(Y);
     dev_free(dY);
     dev_free(dBp);
+    dev_free(dB);
     dev_free(vals);
     dev_free(dvals);
   }
@@ -290,8 +292,8 @@ static int tune_one(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt, Tune
   auto run = [&](const shiro_tuning_t& t) -> int {
     if (kernel == SHIRO_KERNEL_SPMM)
       return launch_spmm(plan, t, b.vals, b.Bp, N, N, dt, b.Y, N, dt == SHIRO_F32 ? SHIRO_F32 : SHIRO_BF16, s);
-    if (kernel == SHIRO_KERNEL_SPMM_T)
-      return launch_spmm_t(plan, t, b.vals, b.dY, N, N, dt, b.dBp, N, nullptr, 0, b.Bp, N, b.dvals,
+    if (kernel == SHIRO_KERNEL_SPMM_T)  // the form autograd uses: dB add-scatter and dvals
+      return launch_spmm_t(plan, t, b.vals, b.dY, N, N, dt, nullptr, 0, b.dB, N, b.Bp, N, b.dvals,
                            nullptr, s);
     return launch_sddmm(plan, t, b.vals, b.dY, N, b.Bp, N, N, dt, b.dvals, s);
   };
@@ -616,6 +618,11 @@ SHIRO_API int shiro_autotune(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_
   SHIRO_TRY(dev_alloc(&b.Y, R * N * 4));
   SHIRO_TRY(dev_alloc(&b.dY, R * N * 4));
   SHIRO_TRY(dev_alloc(&b.dBp, U * N * 4));
+  if (ops & SHIRO_OP_BACKWARD) {
+    // scratch dB of the full B shape (only the selected rows are touched)
+    SHIRO_TRY(dev_alloc(&b.dB, plan->n_cols * N * sz));
+    SHIRO_TRY(launch_fill_random((float*)b.dB, plan->n_cols * N * sz / 4, 4, s));
+  }
   SHIRO_TRY(dev_alloc_n(&b.vals, plan->nz_begin + nnz));
   SHIRO_TRY(dev_alloc_n(&b.dvals, plan->nz_begin + nnz));
   SHIRO_TRY(launch_fill_random((float*)b.Bp, U * N * sz / 4, 1, s));
