@@ -68,9 +68,10 @@ def make_workload(name, dev):
 
 
 def src_hash(*names):
+    """Short hash of package files (paths relative to the package)."""
     h = hashlib.sha256()
     for n in names:
-        with open(os.path.join(ROOT, "paper_2512_20178_amd", "csrc", n), "rb") as f:
+        with open(os.path.join(ROOT, "paper_2512_20178_amd", n), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
@@ -164,14 +165,15 @@ def main():
     rp = A.row_ptr[info["row_begin"]: info["row_begin"] + M + 1]
     R_nonempty = int((rp[1:] != rp[:-1]).sum().item())
     # algorithmic bytes: every B / Bpacked / dY row read once, every output row
-    # written once, 8 bytes of index + value per nonzero (SURVEY-style counts)
+    # written once, 4 bytes per index and per value touched
     alg = {
         "select": 8 * nnz + 4 * U + 2 * ((A.n_cols + 7) // 8),
         "pack_B": 2 * U * N * sz,
         "spmm": 8 * (M + 1) + 8 * nnz + U * N * sz + M * N * sz,
         # A^T dY add-scattered into dB (read + write of the U selected rows) and
-        # dvals, in one pass over the transposed pattern
-        "backward": 8 * (U + 1) + 8 * nnz + 4 * nnz + R_nonempty * N * sz + U * N * sz + 2 * U * N * sz,
+        # dvals, in one pass over the transposed pattern: row pointers, row ids,
+        # CSR positions, values read, dvals written
+        "backward": 8 * (U + 1) + 16 * nnz + R_nonempty * N * sz + U * N * sz + 2 * U * N * sz,
     }
     ops = {
         "select": lambda: shiro.refresh_selection(plan),
@@ -202,7 +204,8 @@ def main():
     if os.path.exists(pmc_path):
         with open(pmc_path) as f:
             pmc = json.load(f)
-        if pmc.get("src_hash") == src_hash("spmm.hip", "common.hpp"):
+        # counters taken on another build of these kernels or another tuning are stale
+        if pmc.get("src_hash") == src_hash("csrc/spmm.hip", "csrc/common.hpp", "csrc/capi.hip", "tuning_mi355x.txt"):
             traffic = pmc.get("hbm_bytes_per_launch")
     kernels_of = {"pack_B": "k_pack", "spmm": "k_spmm + k_fixup",
                   "backward": "k_gather_vals + k_spmm<dot> + k_fixup + k_scatter_vals"}
@@ -229,6 +232,7 @@ def main():
         "step_hbm_frac": round(alg_step / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "kernels_us": {k: round(v, 2) for k, v in kern_us.items()},
         "kernels_hbm_frac": {k: round(alg[k] / (kern_us[k] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) for k in kern_us},
+        "algorithmic_bytes": {k: int(v) for k, v in alg.items()},
         "setup_ms": {"partition": round(t_part * 1e3, 2), "select_rows": round(t_sel * 1e3, 2)},
     }
 
@@ -322,9 +326,10 @@ def host_csr(A):
 
 def cpu_baseline(A, B, G, N, args, out):
     """The FP64 oracle on the host cores: select, pack, spmm, A^T dY and
-    dvals.  The sample is the whole panel when it has at most 6M nonzeros
-    (about 10-30 s of oracle work), else the leading rows of the panel up to
-    6M nonzeros (only for one-block workloads, P = 1)."""
+    dvals.  The sample is the whole panel when it has at most 6M nonzeros,
+    else the leading rows of the panel up to 6M nonzeros (only for one-block
+    workloads, P = 1); it is run repeatedly until about 10 s of host time
+    have passed, and the rate is the mean over those runs."""
     import numpy as np
 
     import oracle
@@ -337,17 +342,20 @@ def cpu_baseline(A, B, G, N, args, out):
         Ac = oracle.Csr(r1, A.n_cols, rp[: r1 + 1], Ac.col[: rp[r1]], Ac.vals[: rp[r1]], 1, 0)
     Bh = B.float().cpu().numpy()
     Gh = G[: Ac.M].float().cpu().numpy()
-    t = time.perf_counter()
-    uc, off, cm = oracle.select(Ac)
-    Bp = oracle.pack(Bh, uc)
-    oracle.spmm(Ac, Bp, cm)
-    oracle.spmm_t(Ac, Gh, cm, n_out=len(uc))
-    oracle.sddmm(Ac, Gh, Bp, cm)
-    dt = time.perf_counter() - t
-    flops = 3 * 2.0 * Ac.nnz_panel * N
+    runs, dt = 0, 0.0
+    while dt < 10.0 and runs < 1000:
+        t = time.perf_counter()
+        uc, off, cm = oracle.select(Ac)
+        Bp = oracle.pack(Bh, uc)
+        oracle.spmm(Ac, Bp, cm)
+        oracle.spmm_t(Ac, Gh, cm, n_out=len(uc))
+        oracle.sddmm(Ac, Gh, Bp, cm)
+        dt += time.perf_counter() - t
+        runs += 1
+    flops = 3 * 2.0 * Ac.nnz_panel * N * runs
     return {"value": round(flops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.threads(), "kind": "oracle",
             "sample": f"rows [{Ac.row_begin},{Ac.row_end}) of {args.workload} ({Ac.nnz_panel} nonzeros, "
-                      f"P={Ac.P}, N={N}): select+pack+spmm+A^T dY+dvals in FP64, one run, {dt:.2f} s",
+                      f"P={Ac.P}, N={N}): select+pack+spmm+A^T dY+dvals in FP64, {runs} runs, {dt:.2f} s",
             "seconds": round(dt, 3)}
 
 
