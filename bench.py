@@ -4,7 +4,7 @@
 A step is one pass of the whole path over the workload: select (the
 selection kernels, re-run on the device), pack_B, spmm (all column blocks in
 one launch) and spmm_backward (the gradients autograd needs: A^T dY
-add-scattered into dB at the selected rows, and dvals),
+written into the selected rows of a zero-filled dB, and dvals),
 captured once in a HIP graph and replayed.  Inputs are resident in HBM
 before timing starts.  The metric counts 2*nnz*N flops for each of the three
 products of a step (Y, dBpacked, dvals).
@@ -131,7 +131,7 @@ def main():
         shiro.refresh_selection(plan)
         shiro.pack_B(plan, B, out=Bp)
         shiro.spmm(plan, vals, Bp, out=Y)
-        shiro.spmm_backward(plan, vals, G, Bp, dB=dB, dvals=dvals)
+        shiro.spmm_backward(plan, vals, G, Bp, dB=dB, dvals=dvals, dB_overwrite=True)
 
     # ---- capture one step as a HIP graph ----
     cs = torch.cuda.Stream()
@@ -170,16 +170,16 @@ def main():
         "select": 8 * nnz + 4 * U + 2 * ((A.n_cols + 7) // 8),
         "pack_B": 2 * U * N * sz,
         "spmm": 8 * (M + 1) + 8 * nnz + U * N * sz + M * N * sz,
-        # A^T dY add-scattered into dB (read + write of the U selected rows) and
-        # dvals, in one pass over the transposed pattern: row pointers, row ids,
-        # CSR positions, values read, dvals written
-        "backward": 8 * (U + 1) + 16 * nnz + R_nonempty * N * sz + U * N * sz + 2 * U * N * sz,
+        # A^T dY written into the U selected rows of dB, and dvals, in one
+        # pass over the transposed pattern: row pointers, row ids, CSR
+        # positions, values read, dvals written; dY rows and Bpacked read once
+        "backward": 8 * (U + 1) + 16 * nnz + R_nonempty * N * sz + U * N * sz + U * N * sz,
     }
     ops = {
         "select": lambda: shiro.refresh_selection(plan),
         "pack_B": lambda: shiro.pack_B(plan, B, out=Bp),
         "spmm": lambda: shiro.spmm(plan, vals, Bp, out=Y),
-        "backward": lambda: shiro.spmm_backward(plan, vals, G, Bp, dB=dB, dvals=dvals),
+        "backward": lambda: shiro.spmm_backward(plan, vals, G, Bp, dB=dB, dvals=dvals, dB_overwrite=True),
     }
     reps = 10
     kern_us = {}
@@ -227,7 +227,7 @@ def main():
         "dtype": args.dtype,
         "data": "synthetic",
         "config": {"workload": args.workload, "n": A.n_rows, "P": A.P, "p": A.p, "rows": M, "nnz": nnz,
-                   "U": U, "N": N, "step": "select+pack_B+spmm+spmm_backward(dB scatter, dvals)"},
+                   "U": U, "N": N, "step": "select+pack_B+spmm+spmm_backward(dB rows, dvals)"},
         "roofline": roofline,
         "step_hbm_frac": round(alg_step / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "kernels_us": {k: round(v, 2) for k, v in kern_us.items()},
@@ -282,7 +282,7 @@ def main():
                 shiro.refresh_selection(plan)
                 shiro.pack_B(plan, Bh, out=Bph)
                 shiro.spmm(plan, vals, Bph, out=Yh)
-                shiro.spmm_backward(plan, vals, Gh, Bph, dB=dBh, dvals=dvals)
+                shiro.spmm_backward(plan, vals, Gh, Bph, dB=dBh, dvals=dvals, dB_overwrite=True)
 
             if not args.no_autotune:
                 shiro.autotune(plan, N, torch.bfloat16, ops=("spmm", "backward"))
@@ -292,7 +292,7 @@ def main():
             out["bf16_kernels_us"] = {
                 "pack_B": round(timed(lambda: shiro.pack_B(plan, Bh, out=Bph)), 2),
                 "spmm": round(timed(lambda: shiro.spmm(plan, vals, Bph, out=Yh)), 2),
-                "backward": round(timed(lambda: shiro.spmm_backward(plan, vals, Gh, Bph, dB=dBh, dvals=dvals)), 2),
+                "backward": round(timed(lambda: shiro.spmm_backward(plan, vals, Gh, Bph, dB=dBh, dvals=dvals, dB_overwrite=True)), 2),
             }
             del Bh, Gh, Bph, Yh, dBh
         # sampled parity of Y at full size against the FP64 oracle

@@ -98,6 +98,9 @@ enum {
 #define SHIRO_MODE_BATCHED 0u   /* all column blocks in one persistent launch, row-merged */
 #define SHIRO_MODE_PER_BLOCK 1u /* one launch per column block, summed in block order     */
 
+/* shiro_spmm_backward flags */
+#define SHIRO_DB_OVERWRITE 1u /* dB rows at unique_cols are overwritten instead of added to */
+
 /* shiro_prepare / shiro_autotune operation mask */
 #define SHIRO_OP_SPMM 1u
 #define SHIRO_OP_BACKWARD 2u
@@ -212,19 +215,26 @@ SHIRO_API int shiro_spmm(shiro_plan plan, const float* d_vals, const void* d_Bpa
                          int64_t ldp, int32_t N, shiro_dtype in_dt, void* d_Y, int64_t ldy,
                          shiro_dtype out_dt, uint32_t mode, shiro_stream_t stream);
 
-/* Backward of Y = A Bpacked for a loss with upstream gradient dY (M x N):
+/* Backward of Y = A Bpacked for a loss with upstream gradient dY (M x N);
+ * the two gradients of <dY, A B> (the adjoint of the product of Sec. 2.1):
  *   dBpacked = A^T dY                       (U x N, overwritten; nullable)
  *   dB[unique_cols[u], :] += dBpacked[u, :] (n_cols x N, read-modify-write into
  *                                            the caller's buffer; nullable)
+ *     or, with flags & SHIRO_DB_OVERWRITE,
+ *   dB[unique_cols[u], :]  = dBpacked[u, :] (the other rows of dB are not
+ *                                            touched: a zero-filled dB then
+ *                                            holds the full gradient)
  *   dvals[k] = dY[i(k), :] . Bpacked[colmap[k], :]  (float32 per nonzero,
  *                                            indexed like d_vals; nullable)
  * A^T is applied through a transposed pattern built once per plan by a stable
  * radix sort (no atomics).  dt applies to dY, Bpacked, dBpacked and dB
- * (F32 or BF16; arithmetic float32).  NOT_READY before select_rows. */
+ * (F32 or BF16; arithmetic float32).  Unknown flag bits: INVALID_ARG.
+ * NOT_READY before select_rows. */
 SHIRO_API int shiro_spmm_backward(shiro_plan plan, const float* d_vals, const void* d_dY,
                                   int64_t lddy, const void* d_Bpacked, int64_t ldp, int32_t N,
                                   shiro_dtype dt, void* d_dBpacked, int64_t lddbp, void* d_dB,
-                                  int64_t lddb, float* d_dvals, shiro_stream_t stream);
+                                  int64_t lddb, float* d_dvals, uint32_t flags,
+                                  shiro_stream_t stream);
 
 /* Build everything the per-call steps need for (N, dtype, ops) - work lists,
  * transposed pattern, carry buffers - so later calls neither allocate nor
@@ -235,7 +245,7 @@ SHIRO_API int shiro_prepare(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t
 /* Time candidate tunings of the kernels in `ops` on scratch data of the
  * plan's shape at width N and keep the fastest per kernel in the plan (the
  * median of nine runs ranks each candidate).  The backward is tuned in the
- * form autograd uses (dB add-scatter plus dvals), on a scratch dB of
+ * form autograd uses (dB rows overwritten, plus dvals), on a scratch dB of
  * n_cols x N.  If the environment variable SHIRO_TUNE_CACHE names a file,
  * results are read from it (no timing for keys it holds) and new results are
  * appended (one line per key).  Allocates and synchronises. */

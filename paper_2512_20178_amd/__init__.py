@@ -211,10 +211,12 @@ def spmm(plan: Plan, vals: torch.Tensor, Bpacked: torch.Tensor, out: Optional[to
 
 def spmm_backward(plan: Plan, vals: torch.Tensor, dY: torch.Tensor, Bpacked: Optional[torch.Tensor],
                   dBpacked: Optional[torch.Tensor] = None, dB: Optional[torch.Tensor] = None,
-                  dvals: Optional[torch.Tensor] = None, stream=None):
+                  dvals: Optional[torch.Tensor] = None, stream=None, dB_overwrite: bool = False):
     """dBpacked = A^T dY (overwrite), dB[unique_cols] += dBpacked, dvals = SDDMM(dY, Bpacked).
 
-    Pass the output tensors to compute; None skips an output."""
+    Pass the output tensors to compute; None skips an output.  With
+    dB_overwrite the rows dB[unique_cols] are overwritten instead of added to
+    (the other rows are left as they are)."""
     _dev(dY)
     N = dY.shape[1]
     dt = _dt(dY.dtype)
@@ -224,7 +226,8 @@ def spmm_backward(plan: Plan, vals: torch.Tensor, dY: torch.Tensor, Bpacked: Opt
     _lib.check(_L().shiro_spmm_backward(
         plan.handle, _ptr(vals), _ptr(dY), _ld(dY), _ptr(Bpacked), _ld(Bpacked) if Bpacked is not None else N,
         N, dt, _ptr(dBpacked), _ld(dBpacked) if dBpacked is not None else N, _ptr(dB),
-        _ld(dB) if dB is not None else N, _ptr(dvals), ctypes.c_void_p(_stream(stream))))
+        _ld(dB) if dB is not None else N, _ptr(dvals), _lib.DB_OVERWRITE if dB_overwrite else 0,
+        ctypes.c_void_p(_stream(stream))))
     return dBpacked, dB, dvals
 
 
@@ -293,7 +296,8 @@ class ShiroSpMM(torch.autograd.Function):
             dvals = torch.zeros_like(vals)
         if ctx.needs_input_grad[1]:
             dB = torch.zeros(ctx.B_shape, dtype=ctx.B_dtype, device=dY.device)
-        spmm_backward(plan, vals, dY, Bp, None, dB, dvals)
+        # dB is zero-filled here, so its selected rows are simply written
+        spmm_backward(plan, vals, dY, Bp, None, dB, dvals, dB_overwrite=True)
         return dvals, dB, None, None
 
 

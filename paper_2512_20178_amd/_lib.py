@@ -32,6 +32,7 @@ BF16 = 1
 MODE_BATCHED = 0
 MODE_PER_BLOCK = 1
 
+DB_OVERWRITE = 1
 OP_SPMM = 1
 OP_BACKWARD = 2
 OP_PER_BLOCK = 4
@@ -133,7 +134,8 @@ def load(path: str = LIB_PATH):
         L.shiro_copy_selection.argtypes = [_p, _p, _p, _p, _p]
         L.shiro_pack_B.argtypes = [_p, _p, _i64, _i32, ctypes.c_int, _p, _i64, _p]
         L.shiro_spmm.argtypes = [_p, _p, _p, _i64, _i32, ctypes.c_int, _p, _i64, ctypes.c_int, _u32, _p]
-        L.shiro_spmm_backward.argtypes = [_p, _p, _p, _i64, _p, _i64, _i32, ctypes.c_int, _p, _i64, _p, _i64, _p, _p]
+        L.shiro_spmm_backward.argtypes = [_p, _p, _p, _i64, _p, _i64, _i32, ctypes.c_int, _p, _i64, _p, _i64, _p,
+                                          ctypes.c_uint32, _p]
         L.shiro_prepare.argtypes = [_p, _i32, ctypes.c_int, _u32, _p]
         L.shiro_autotune.argtypes = [_p, _i32, ctypes.c_int, _u32, _p]
         L.shiro_get_tuning.argtypes = [_p, _i32, _i32, ctypes.c_int, ctypes.POINTER(Tuning)]

@@ -292,9 +292,9 @@ static int tune_one(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt, Tune
   auto run = [&](const shiro_tuning_t& t) -> int {
     if (kernel == SHIRO_KERNEL_SPMM)
       return launch_spmm(plan, t, b.vals, b.Bp, N, N, dt, b.Y, N, dt == SHIRO_F32 ? SHIRO_F32 : SHIRO_BF16, s);
-    if (kernel == SHIRO_KERNEL_SPMM_T)  // the form autograd uses: dB add-scatter and dvals
-      return launch_spmm_t(plan, t, b.vals, b.dY, N, N, dt, nullptr, 0, b.dB, N, b.Bp, N, b.dvals,
-                           nullptr, s);
+    if (kernel == SHIRO_KERNEL_SPMM_T)  // the form autograd uses: dB rows overwritten, and dvals
+      return launch_spmm_t(plan, t, b.vals, b.dY, N, N, dt, nullptr, 0, b.dB, N, true, b.Bp, N,
+                           b.dvals, nullptr, s);
     return launch_sddmm(plan, t, b.vals, b.dY, N, b.Bp, N, N, dt, b.dvals, s);
   };
   shiro_tuning_t best = default_tuning(kernel, N, dt);
@@ -542,8 +542,9 @@ SHIRO_API int shiro_spmm(shiro_plan plan, const float* d_vals, const void* d_Bpa
 SHIRO_API int shiro_spmm_backward(shiro_plan plan, const float* d_vals, const void* d_dY, int64_t lddy,
                                   const void* d_Bpacked, int64_t ldp, int32_t N, shiro_dtype dt,
                                   void* d_dBpacked, int64_t lddbp, void* d_dB, int64_t lddb,
-                                  float* d_dvals, shiro_stream_t stream) {
+                                  float* d_dvals, uint32_t flags, shiro_stream_t stream) {
   if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "spmm_backward: plan is NULL");
+  if (flags & ~SHIRO_DB_OVERWRITE) return set_error(SHIRO_ERR_INVALID_ARG, "spmm_backward: unknown flags");
   if (!plan->selected) return set_error(SHIRO_ERR_NOT_READY, "spmm_backward: call shiro_select_rows first");
   if (!valid_dt(dt)) return set_error(SHIRO_ERR_UNSUPPORTED, "spmm_backward: unknown dtype");
   if (N < 0 || lddy < N) return set_error(SHIRO_ERR_INVALID_ARG, "spmm_backward: need N >= 0 and lddy >= N");
@@ -559,7 +560,8 @@ SHIRO_API int shiro_spmm_backward(shiro_plan plan, const float* d_vals, const vo
   bool dvals_done = false;
   if (d_dBpacked || d_dB)
     SHIRO_TRY(launch_spmm_t(plan, tuning_for(plan, SHIRO_KERNEL_SPMM_T, N, dt), d_vals, d_dY, lddy, N,
-                            dt, d_dBpacked, lddbp, d_dB, lddb, d_Bpacked, ldp, d_dvals, &dvals_done, s));
+                            dt, d_dBpacked, lddbp, d_dB, lddb, (flags & SHIRO_DB_OVERWRITE) != 0, d_Bpacked,
+                            ldp, d_dvals, &dvals_done, s));
   if (d_dvals && !dvals_done) {
     if (N == 0) {
       // dvals of an empty product are zero

@@ -157,8 +157,8 @@ int launch_spmm_per_block(shiro_plan plan, const float* vals, const void* X, int
 // covers N, the value gradients are computed in the same pass (*dvals_done).
 int launch_spmm_t(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* dY,
                   int64_t lddy, int32_t N, shiro_dtype dt, void* dBp, int64_t lddbp, void* dB,
-                  int64_t lddb, const void* Bp, int64_t ldp, float* dvals, bool* dvals_done,
-                  hipStream_t s);
+                  int64_t lddb, bool db_overwrite, const void* Bp, int64_t ldp, float* dvals,
+                  bool* dvals_done, hipStream_t s);
 int launch_sddmm(shiro_plan plan, const shiro_tuning_t& t, const float* vals_unused,
                  const void* dY, int64_t lddy, const void* Bp, int64_t ldp, int32_t N,
                  shiro_dtype dt, float* dvals, hipStream_t s);

@@ -109,8 +109,9 @@ struct SpmmArgs {
   int64_t ldx;
   void* out;                // R x N, may be null (transposed: dBpacked optional)
   int64_t ldo;
-  void* scat;               // transposed only: dB, add-scatter at rows scat_idx[r]
+  void* scat;               // transposed only: dB, rows scat_idx[r] (see scat_mode)
   int64_t lds;
+  int32_t scat_mode;        // 1: add the row into dB, 2: overwrite the dB row
   const int32_t* scat_idx;  // R
   const int32_t* chunk_row;  // W + 1
   const int32_t* chunk_nz;   // W + 1
@@ -127,21 +128,25 @@ struct SpmmArgs {
       const TIN *__restrict__ X, int64_t ldx, TOUT *__restrict__ out, int64_t ldo,           \
       TOUT *__restrict__ scat, int64_t lds, const int32_t *__restrict__ scat_idx,             \
       const int32_t *__restrict__ chunk_row, const int32_t *__restrict__ chunk_nz,            \
-      float *__restrict__ carry, int32_t W, int32_t R, int32_t N, int32_t cpw, int32_t xcd_remap
+      float *__restrict__ carry, int32_t W, int32_t R, int32_t N, int32_t cpw, int32_t xcd_remap, \
+      int32_t scat_mode
 
 #define SHIRO_SPMM_ARGS(TIN, TOUT, a)                                                          \
   (a).ptr, (a).idx, (a).vals, reinterpret_cast<const TIN*>((a).D), (a).ldd, (a).dot_out,      \
       reinterpret_cast<const TIN*>((a).X), (a).ldx,                                            \
       reinterpret_cast<TOUT*>((a).out), (a).ldo, reinterpret_cast<TOUT*>((a).scat), (a).lds,   \
       (a).scat_idx, (a).chunk_row, (a).chunk_nz, (a).carry, (a).W, (a).R, (a).N,               \
-      (a).chunks_per_wave, (a).xcd_remap
+      (a).chunks_per_wave, (a).xcd_remap, (a).scat_mode
 
 template <typename TOUT, int VEC>
 __device__ __forceinline__ void epilogue_row(TOUT* __restrict__ out, int64_t ldo, TOUT* __restrict__ scat,
                                              int64_t lds, const int32_t* __restrict__ scat_idx,
-                                             int32_t r, int64_t c, const float (&acc)[VEC]) {
+                                             int32_t scat_mode, int32_t r, int64_t c,
+                                             const float (&acc)[VEC]) {
   if (out) Elem<TOUT>::template store<VEC>(out + (int64_t)r * ldo + c, acc);
-  if (scat) {
+  if (scat && scat_mode == 2) {
+    Elem<TOUT>::template store<VEC>(scat + (int64_t)scat_idx[r] * lds + c, acc);
+  } else if (scat) {
     TOUT* o = scat + (int64_t)scat_idx[r] * lds + c;
     float cur[VEC];
     Elem<TOUT>::template load<VEC>(o, cur);
@@ -164,7 +169,7 @@ __device__ __forceinline__ int32_t logical_block(int32_t remap) {
 // pattern row's own dense row D[r]: in the transposed product this is the
 // gradient of the values, dvals = dY[row] . Bpacked[u], computed from the
 // same dY gathers (no second pass over the nonzeros).
-template <typename TIN, typename TOUT, int LANES, int VEC, int UNROLL, bool DOT, bool SCAT>
+template <typename TIN, typename TOUT, int LANES, int VEC, int UNROLL, bool DOT, int SCAT>
 __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
   constexpr int G = kWave / LANES;
   constexpr int STEP = G * UNROLL;
@@ -206,7 +211,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
       const bool next_nonempty = has_next && ke2 > re;
       // the add-scatter target is read now so its latency hides behind the gathers
       float pre[VEC];
-      if constexpr (SCAT) {
+      if constexpr (SCAT == 1) {
         if (complete) Elem<TOUT>::template load<VEC>(scat + (int64_t)sidx * lds + cl, pre);
       }
       float acc[VEC];
@@ -285,10 +290,12 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
       if (g == 0 && cvalid) {
         if (complete) {
           if (out) Elem<TOUT>::template store<VEC>(out + (int64_t)r * ldo + c, acc);
-          if constexpr (SCAT) {
+          if constexpr (SCAT == 1) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) pre[e] += acc[e];
             Elem<TOUT>::template store<VEC>(scat + (int64_t)sidx * lds + c, pre);
+          } else if constexpr (SCAT == 2) {
+            Elem<TOUT>::template store<VEC>(scat + (int64_t)sidx * lds + c, acc);
           }
         } else {
           float* cs = carry + ((int64_t)w * 2 + (head ? 0 : 1)) * N + c;
@@ -307,7 +314,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
 // rows at once instead of one.  Row bookkeeping is per group (vector
 // registers); groups diverge only in their trip counts.  The order of the
 // sums inside a row is fixed by the row, so results stay reproducible.
-template <typename TIN, typename TOUT, int LANES, int VEC, int UNROLL, bool DOT, bool SCAT>
+template <typename TIN, typename TOUT, int LANES, int VEC, int UNROLL, bool DOT, int SCAT>
 __global__ __launch_bounds__(kBlock) void k_spmm_grp(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
   constexpr int G = kWave / LANES;
   const int lane = lane_id();
@@ -333,7 +340,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_grp(SHIRO_SPMM_PARAMS(TIN, TOUT
       const bool tail = (r == i1);
       const bool complete = !head && !tail;
       float pre[VEC];
-      if constexpr (SCAT) {
+      if constexpr (SCAT == 1) {
         if (complete) Elem<TOUT>::template load<VEC>(scat + (int64_t)scat_idx[r] * lds + cl, pre);
       }
       float d[VEC];
@@ -382,10 +389,12 @@ __global__ __launch_bounds__(kBlock) void k_spmm_grp(SHIRO_SPMM_PARAMS(TIN, TOUT
       if (cvalid) {
         if (complete) {
           if (out) Elem<TOUT>::template store<VEC>(out + (int64_t)r * ldo + c, acc);
-          if constexpr (SCAT) {
+          if constexpr (SCAT == 1) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) pre[e] += acc[e];
             Elem<TOUT>::template store<VEC>(scat + (int64_t)scat_idx[r] * lds + c, pre);
+          } else if constexpr (SCAT == 2) {
+            Elem<TOUT>::template store<VEC>(scat + (int64_t)scat_idx[r] * lds + c, acc);
           }
         } else {
           float* cs = carry + ((int64_t)w * 2 + (head ? 0 : 1)) * N + c;
@@ -434,7 +443,7 @@ __global__ __launch_bounds__(kBlock) void k_fixup(SHIRO_SPMM_PARAMS(TIN, TOUT),
         for (int32_t q = 1; q < S; ++q)
 #pragma unroll
           for (int e = 0; e < VEC; ++e) acc[e] += part[(q * lanes_per_row + li) * VEC + e];
-        epilogue_row<TOUT, VEC>(out, ldo, scat, lds, scat_idx, r, c, acc);
+        epilogue_row<TOUT, VEC>(out, ldo, scat, lds, scat_idx, scat_mode, r, c, acc);
       }
     }
   }
@@ -763,7 +772,7 @@ int grid_waves(shiro_plan plan, const shiro_tuning_t& t, int32_t W, int32_t* chu
   return SHIRO_OK;
 }
 
-template <typename TIN, typename TOUT, int VEC, bool DOT, bool SCAT>
+template <typename TIN, typename TOUT, int VEC, bool DOT, int SCAT>
 int spmm_dispatch(const shiro_tuning_t& t, dim3 grid, hipStream_t s, const SpmmArgs& a) {
 #define SHIRO_SPMM_CASE(L, U)                                                                          \
   if (t.lanes == L && t.unroll == U) {                                                                 \
@@ -819,21 +828,28 @@ int run_spmm_family(shiro_plan plan, shiro_tuning_t t, const WorkList* wl, SpmmA
   a.xcd_remap = t.xcd_remap;
   dim3 grid(nb, ntiles);
   constexpr int V16 = Elem<TIN>::kVec16;
+  const bool store = a.scat_mode == 2;
   if (a.dot_out) {
     if (ntiles != 1) return set_error(SHIRO_ERR_UNSUPPORTED, "fused dvals needs one column tile");
-    if (a.scat) {
-      if (vec == V16) SHIRO_TRY((spmm_dispatch<TIN, TOUT, V16, true, true>(t, grid, s, a)));
-      else SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1, true, true>(t, grid, s, a)));
+    if (a.scat && store) {
+      if (vec == V16) SHIRO_TRY((spmm_dispatch<TIN, TOUT, V16, true, 2>(t, grid, s, a)));
+      else SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1, true, 2>(t, grid, s, a)));
+    } else if (a.scat) {
+      if (vec == V16) SHIRO_TRY((spmm_dispatch<TIN, TOUT, V16, true, 1>(t, grid, s, a)));
+      else SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1, true, 1>(t, grid, s, a)));
     } else {
-      if (vec == V16) SHIRO_TRY((spmm_dispatch<TIN, TOUT, V16, true, false>(t, grid, s, a)));
-      else SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1, true, false>(t, grid, s, a)));
+      if (vec == V16) SHIRO_TRY((spmm_dispatch<TIN, TOUT, V16, true, 0>(t, grid, s, a)));
+      else SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1, true, 0>(t, grid, s, a)));
     }
+  } else if (a.scat && store) {
+    if (vec == V16) SHIRO_TRY((spmm_dispatch<TIN, TOUT, V16, false, 2>(t, grid, s, a)));
+    else SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1, false, 2>(t, grid, s, a)));
   } else if (a.scat) {
-    if (vec == V16) SHIRO_TRY((spmm_dispatch<TIN, TOUT, V16, false, true>(t, grid, s, a)));
-    else SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1, false, true>(t, grid, s, a)));
+    if (vec == V16) SHIRO_TRY((spmm_dispatch<TIN, TOUT, V16, false, 1>(t, grid, s, a)));
+    else SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1, false, 1>(t, grid, s, a)));
   } else {
-    if (vec == V16) SHIRO_TRY((spmm_dispatch<TIN, TOUT, V16, false, false>(t, grid, s, a)));
-    else SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1, false, false>(t, grid, s, a)));
+    if (vec == V16) SHIRO_TRY((spmm_dispatch<TIN, TOUT, V16, false, 0>(t, grid, s, a)));
+    else SHIRO_TRY((spmm_dispatch<TIN, TOUT, 1, false, 0>(t, grid, s, a)));
   }
   if (wl->nsplit == 0) return SHIRO_OK;
   const unsigned fb = (unsigned)std::min<int64_t>(wl->nsplit, 65536);
@@ -1085,8 +1101,8 @@ int launch_spmm(shiro_plan plan, const shiro_tuning_t& t, const float* vals, con
 
 int launch_spmm_t(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* dY,
                   int64_t lddy, int32_t N, shiro_dtype dt, void* dBp, int64_t lddbp, void* dB,
-                  int64_t lddb, const void* Bp, int64_t ldp, float* dvals, bool* dvals_done,
-                  hipStream_t s) {
+                  int64_t lddb, bool db_overwrite, const void* Bp, int64_t ldp, float* dvals,
+                  bool* dvals_done, hipStream_t s) {
   if (dvals_done) *dvals_done = false;
   if (plan->U == 0 || N == 0 || (!dBp && !dB)) return SHIRO_OK;
   const bool cap = stream_capturing(s);
@@ -1113,6 +1129,7 @@ int launch_spmm_t(shiro_plan plan, const shiro_tuning_t& t, const float* vals, c
   a.ldo = lddbp;
   a.scat = dB;
   a.lds = lddb;
+  a.scat_mode = db_overwrite ? 2 : 1;
   a.scat_idx = plan->unique_cols;
   a.chunk_row = wl->chunk_row;
   a.chunk_nz = wl->chunk_nz;

@@ -85,7 +85,7 @@ def test_null_plan_errors(lib):
     assert lib.shiro_select_rows(P, None, None, None) == -1
     assert lib.shiro_pack_B(P, None, 0, 0, 0, None, 0, None) == -1
     assert lib.shiro_spmm(P, None, None, 0, 0, 0, None, 0, 0, 0, None) == -1
-    assert lib.shiro_spmm_backward(P, None, None, 0, None, 0, 0, 0, None, 0, None, 0, None, None) == -1
+    assert lib.shiro_spmm_backward(P, None, None, 0, None, 0, 0, 0, None, 0, None, 0, None, 0, None) == -1
     assert lib.shiro_prepare(P, 1, 0, 1, None) == -1
     assert lib.shiro_autotune(P, 1, 0, 1, None) == -1
     assert lib.shiro_plan_info(P, None) == -1

@@ -135,6 +135,19 @@ def test_rmat24_spmm_and_backward_sampled(shiro, rmat24):
     dv = oracle.sddmm(Ac, Gh, Bph, cm)
     dvden = oracle.sddmm(Ac, Gh, Bph, cm, abs_mode=True)
     assert oracle.rel_err(dvals.cpu().numpy()[Ac.nz_begin:Ac.nz_begin + Ac.nnz_panel], dv, dvden) <= TOL_F32
+    # the form the benchmark times: selected rows of a zero-filled dB
+    # (n_cols x N) overwritten, dvals fused
+    dB = torch.zeros(A.n_cols, N, device=dev)
+    dvals2 = torch.zeros(A.nnz, device=dev)
+    shiro.spmm_backward(plan, A.vals, G, Bp, dB=dB, dvals=dvals2, dB_overwrite=True)
+    assert torch.equal(dvals2, dvals)
+    got = dB[torch.from_numpy(uc[tgt]).long().to(dev)].cpu().numpy()
+    assert oracle.rel_err(got, ref, rden) <= TOL_F32
+    sel = np.zeros(A.n_cols, bool)
+    sel[uc] = True
+    others = np.flatnonzero(~sel)[rng.integers(0, int((~sel).sum()), 4096)]
+    assert not bool(dB[torch.from_numpy(others).long().to(dev)].any())
+    del dB
 
 
 # ----------------------------------------------------------------------------

@@ -210,6 +210,18 @@ def test_backward_f32(shiro, run):
     dB4 = torch.zeros(run.A.n_cols, run.N, device=dev)
     shiro.spmm_backward(run.plan, run.Ad.vals, dY, None, dB=dB4)
     assert oracle.rel_err(dB4.cpu().numpy()[run.uc], rdBp, rden) <= TOL_F32
+    # overwrite form: selected rows of dB replaced, the others untouched,
+    # with and without the fused dvals
+    for with_dvals in (True, False):
+        dB5 = base.to(dev)
+        dvals5 = torch.zeros_like(dvals)
+        shiro.spmm_backward(run.plan, run.Ad.vals, dY, Bp if with_dvals else None, dB=dB5,
+                            dvals=dvals5 if with_dvals else None, dB_overwrite=True)
+        got5 = dB5.cpu().numpy()
+        assert oracle.rel_err(got5[run.uc], rdBp, rden) <= TOL_F32
+        assert np.array_equal(got5[mask], base.numpy()[mask])
+        if with_dvals:
+            assert torch.equal(dvals5, dvals)
 
 
 def test_backward_bf16(shiro, run):
@@ -226,6 +238,14 @@ def test_backward_bf16(shiro, run):
     assert oracle.rel_err(bf16_to_f32(dB)[run.uc], rdBp, rden) <= TOL_BF16
     gv = dvals.cpu().numpy()[run.Ac.nz_begin:run.Ac.nz_begin + run.Ac.nnz_panel]
     assert oracle.rel_err(gv, rdv, rdv_den) <= TOL_BF16
+    # overwrite form on a buffer of ones: selected rows equal the add form's
+    # result on zeros (one rounding either way), the others stay one
+    dB2 = torch.ones(run.A.n_cols, run.N, dtype=torch.bfloat16, device=dev)
+    shiro.spmm_backward(run.plan, run.Ad.vals, Gh.to(dev), Bp, dB=dB2, dvals=dvals, dB_overwrite=True)
+    mask = torch.ones(run.A.n_cols, dtype=torch.bool)
+    mask[torch.from_numpy(run.uc).long()] = False
+    assert torch.equal(dB2.cpu()[~mask], dB.cpu()[~mask])
+    assert bool((dB2.cpu()[mask] == 1).all())
 
 
 @pytest.mark.parametrize("knobs", [
@@ -253,6 +273,18 @@ def test_tunings_all_correct(shiro, run, knobs):
     assert oracle.rel_err(dBp.cpu().numpy(), rdBp, rden) <= TOL_F32
     gv = dvals.cpu().numpy()[run.Ac.nz_begin:run.Ac.nz_begin + run.Ac.nnz_panel]
     assert oracle.rel_err(gv, rdv, rdv_den) <= TOL_F32
+    # the form autograd uses: dB rows overwritten, dvals fused (carries of cut
+    # rows are stored by the fix-up)
+    dB = torch.full((run.A.n_cols, run.N), 7.0, device=dev)
+    dvals2 = torch.zeros_like(dvals)
+    shiro.spmm_backward(run.plan, run.Ad.vals, run.G.to(dev), Bp, dB=dB, dvals=dvals2, dB_overwrite=True)
+    got = dB.cpu().numpy()
+    assert oracle.rel_err(got[run.uc], rdBp, rden) <= TOL_F32
+    mask = np.ones(run.A.n_cols, bool)
+    mask[run.uc] = False
+    assert bool((got[mask] == 7.0).all())
+    assert oracle.rel_err(dvals2.cpu().numpy()[run.Ac.nz_begin:run.Ac.nz_begin + run.Ac.nnz_panel], rdv,
+                          rdv_den) <= TOL_F32
     for k in ("spmm", "spmm_t", "sddmm"):  # back to the defaults for other tests
         shiro.set_tuning(run.plan, k, run.N, torch.float32, chunk=256 if k != "sddmm" else 512, lanes=64,
                          unroll=2, xcd_remap=0, wg_per_cu=8, group_rows=0)
