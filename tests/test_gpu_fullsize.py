@@ -32,8 +32,14 @@ def shiro():
     import paper_2512_20178_amd as s
 
     s._lib.load()
+    # the launch configuration the benchmark uses: the committed tuning table
+    old = os.environ.get("SHIRO_TUNE_CACHE")
     os.environ.setdefault("SHIRO_TUNE_CACHE", os.path.join(ROOT, "paper_2512_20178_amd", "tuning_mi355x.txt"))
-    return s
+    yield s
+    if old is None:
+        os.environ.pop("SHIRO_TUNE_CACHE", None)
+    else:
+        os.environ["SHIRO_TUNE_CACHE"] = old
 
 
 def host_csr(A):

@@ -360,7 +360,8 @@ def test_autograd_function(shiro):
     assert oracle.rel_err(vals.grad.cpu().numpy(), dv, dvd) <= TOL_F32
 
 
-def test_autotune_then_correct(shiro):
+def test_autotune_then_correct(shiro, monkeypatch, tmp_path):
+    monkeypatch.setenv("SHIRO_TUNE_CACHE", str(tmp_path / "tune.txt"))  # time every candidate here
     A, N = make_case("rmat12_P8_p0")
     dev = torch.device("cuda")
     Ad = A.to(dev)
@@ -376,6 +377,8 @@ def test_autotune_then_correct(shiro):
     Yref = oracle.spmm(Ac, B.cpu().numpy(), None)
     den = oracle.spmm(Ac, B.cpu().numpy(), None, abs_mode=True)
     assert oracle.rel_err(Y.cpu().numpy(), Yref, den) <= TOL_F32
+    lines = (tmp_path / "tune.txt").read_text().splitlines()
+    assert len(lines) == 3 and all(ln.split()[0].endswith(("|k=0", "|k=1", "|k=2")) for ln in lines)
 
 
 def test_error_paths_on_device(shiro):
