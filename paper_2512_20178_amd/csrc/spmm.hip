@@ -209,20 +209,10 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
       const int32_t sidx2 = (SCAT && has_next) ? scat_idx[r + 1] : 0;
       const int64_t ke2 = re2 < j1 ? re2 : j1;
       const bool next_nonempty = has_next && ke2 > re;
-      // the add-scatter target is read now so its latency hides behind the gathers
-      float pre[VEC];
-      if constexpr (SCAT == 1) {
-        if (complete) Elem<TOUT>::template load<VEC>(scat + (int64_t)sidx * lds + cl, pre);
-      }
-      float acc[VEC];
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
-      float d[VEC];
-      if constexpr (DOT) {
-        Elem<TIN>::template load<VEC>(D + (int64_t)r * ldd + cl, d);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) d[e] = cvalid ? d[e] : 0.f;
-      }
+      // Load order matters: loads retire in issue order for the wait
+      // counter, so the first step's indices are issued before the row's own
+      // dense rows (D, the add-scatter target), and nothing reads those until
+      // the gathers are in flight — the gathers then wait on the indices only.
       if (!have && kb < ke) {
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
@@ -234,6 +224,16 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
         }
       }
       have = false;
+      // the add-scatter target is read now so its latency hides behind the gathers
+      float pre[VEC];
+      if constexpr (SCAT == 1) {
+        if (complete) Elem<TOUT>::template load<VEC>(scat + (int64_t)sidx * lds + cl, pre);
+      }
+      float acc[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
+      float d[VEC];  // lanes past N read column 0; their dots are masked below
+      if constexpr (DOT) Elem<TIN>::template load<VEC>(D + (int64_t)r * ldd + cl, d);
       // Software pipeline: the index/value loads of the next step (or of the
       // next row's first step) are issued while this step's row gathers are
       // in flight.  All loads are unconditional (idle slots re-read a valid
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
             float q = 0.f;
 #pragma unroll
             for (int e = 0; e < VEC; ++e) q = fmaf(d[e], x[u][e], q);
-            q = group_sum<LANES>(q);
+            q = group_sum<LANES>(cvalid ? q : 0.f);
             if (li == LANES - 1 && ok[u]) dot_out[k + u * G + g] = q;
           }
         }
@@ -343,12 +343,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_grp(SHIRO_SPMM_PARAMS(TIN, TOUT
       if constexpr (SCAT == 1) {
         if (complete) Elem<TOUT>::template load<VEC>(scat + (int64_t)scat_idx[r] * lds + cl, pre);
       }
-      float d[VEC];
-      if constexpr (DOT) {
-        Elem<TIN>::template load<VEC>(D + (int64_t)r * ldd + cl, d);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) d[e] = cvalid ? d[e] : 0.f;
-      }
+      float d[VEC];  // lanes past N read column 0; their dots are masked below
+      if constexpr (DOT) Elem<TIN>::template load<VEC>(D + (int64_t)r * ldd + cl, d);
       float acc[VEC];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
@@ -381,7 +377,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_grp(SHIRO_SPMM_PARAMS(TIN, TOUT
             float q = 0.f;
 #pragma unroll
             for (int e = 0; e < VEC; ++e) q = fmaf(d[e], x[u][e], q);
-            q = group_sum<LANES>(q);
+            q = group_sum<LANES>(cvalid ? q : 0.f);
             if (li == LANES - 1 && ok[u]) dot_out[k + u] = q;
           }
         }
