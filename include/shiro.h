@@ -122,7 +122,7 @@ typedef struct {
   int32_t chunk;     /* merge-path items (rows + nonzeros) per wavefront       */
   int32_t lanes;     /* lanes sharing one dense row: 8, 16, 32 or 64 (tile width = lanes * 16 bytes) */
   int32_t unroll;    /* nonzeros in flight per lane group: 1, 2 or 4           */
-  int32_t group_rows; /* 1: each lane group of a wavefront owns its own row     */
+  int32_t group_rows; /* 1: each lane group of a wavefront owns its own rows    */
   int32_t xcd_remap; /* 1: give each XCD a contiguous range of work            */
   int32_t wg_per_cu; /* persistent grid: workgroups per compute unit           */
 } shiro_tuning_t;

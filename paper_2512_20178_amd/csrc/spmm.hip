@@ -310,10 +310,13 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
 }
 
 // Variant for short rows: lane group g of a wavefront takes rows i0+g,
-// i0+g+G, ... of the chunk, one nonzero per slot, so a wavefront advances G
-// rows at once instead of one.  Row bookkeeping is per group (vector
-// registers); groups diverge only in their trip counts.  The order of the
-// sums inside a row is fixed by the row, so results stay reproducible.
+// i0+g+G, ... of the chunk, UNROLL nonzeros per step, so a wavefront keeps G
+// rows in flight instead of one.  Each group reads the row pointers of its
+// next row at the start of the current one and that row's first indices
+// during the current row's last step, so a short row costs one dependent
+// round trip (its gathers).  Row bookkeeping is per group (vector
+// registers); groups diverge only in their trip counts.  Sums inside a row
+// keep a fixed order, so results stay reproducible.
 template <typename TIN, typename TOUT, int LANES, int VEC, int UNROLL, bool DOT, int SCAT>
 __global__ __launch_bounds__(kBlock) void k_spmm_grp(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
   constexpr int G = kWave / LANES;
@@ -331,17 +334,41 @@ __global__ __launch_bounds__(kBlock) void k_spmm_grp(SHIRO_SPMM_PARAMS(TIN, TOUT
   for (int32_t w = w_begin; w < w_end; ++w) {
     const int32_t i0 = chunk_row[w], i1 = chunk_row[w + 1];
     const int64_t j0 = chunk_nz[w], j1 = chunk_nz[w + 1];
-    for (int32_t r = i0 + g; r <= i1 && r < R; r += G) {
-      const int64_t rs = ptr[r], re = ptr[r + 1];
+    int32_t r = i0 + g;
+    if (r > i1 || r >= R) continue;
+    int64_t rs = ptr[r], re = ptr[r + 1];
+    int32_t xi[UNROLL];
+    float v[UNROLL];
+    bool ok[UNROLL];
+    bool have = false;
+    for (; r <= i1 && r < R; r += G) {
       if (r == i1 && j1 <= rs) break;  // chunk holds nothing of row i1
       const int64_t kb = rs > j0 ? rs : j0;
       const int64_t ke = re < j1 ? re : j1;
       const bool head = (r == i0) && (j0 > rs);
       const bool tail = (r == i1);
       const bool complete = !head && !tail;
+      const int32_t sidx = SCAT ? scat_idx[r] : 0;
+      // indices first, then the group's next row pointers, then the row's
+      // own dense rows (loads retire in issue order for the wait counter)
+      if (!have && kb < ke) {
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          const int64_t kk = kb + u;
+          ok[u] = kk < ke;
+          const int64_t kc = ok[u] ? kk : ke - 1;
+          xi[u] = idx[kc];
+          v[u] = vals[kc];
+        }
+      }
+      have = false;
+      const int32_t rn = r + G;
+      const bool has_next = rn <= i1 && rn < R;
+      const int64_t rsn = has_next ? ptr[rn] : re;
+      const int64_t ren = has_next ? ptr[rn + 1] : re;
       float pre[VEC];
       if constexpr (SCAT == 1) {
-        if (complete) Elem<TOUT>::template load<VEC>(scat + (int64_t)scat_idx[r] * lds + cl, pre);
+        if (complete) Elem<TOUT>::template load<VEC>(scat + (int64_t)sidx * lds + cl, pre);
       }
       float d[VEC];  // lanes past N read column 0; their dots are masked below
       if constexpr (DOT) Elem<TIN>::template load<VEC>(D + (int64_t)r * ldd + cl, d);
@@ -349,21 +376,30 @@ __global__ __launch_bounds__(kBlock) void k_spmm_grp(SHIRO_SPMM_PARAMS(TIN, TOUT
 #pragma unroll
       for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
       for (int64_t k = kb; k < ke; k += UNROLL) {
-        int32_t xi[UNROLL];
-        float v[UNROLL];
-        bool ok[UNROLL];
-#pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-          const int64_t kk = k + u;
-          ok[u] = kk < ke;
-          const int64_t kc = ok[u] ? kk : ke - 1;
-          xi[u] = idx[kc];
-          v[u] = vals[kc];
-        }
         float x[UNROLL][VEC];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
           Elem<TIN>::template load<VEC>(X + (int64_t)xi[u] * ldx + cl, x[u]);
+        // next step of this row, or the first step of the group's next row
+        const bool same_row = k + UNROLL < ke;
+        const int64_t kbn = rsn > j0 ? rsn : j0;
+        const int64_t ken = ren < j1 ? ren : j1;
+        const bool next_nonempty = has_next && !(rn == i1 && j1 <= rsn) && kbn < ken;
+        const bool pf = same_row || next_nonempty;
+        const int64_t nb = same_row ? k + UNROLL : (next_nonempty ? kbn : kb);
+        const int64_t nl = same_row ? ke : (next_nonempty ? ken : ke);
+        int32_t xin[UNROLL];
+        float vn[UNROLL];
+        bool okn[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          const int64_t kk = nb + u;
+          okn[u] = pf && kk < nl;
+          const int64_t kc = kk < nl ? kk : nl - 1;
+          xin[u] = idx[kc];
+          vn[u] = vals[kc];
+        }
+        have = !same_row && next_nonempty;
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
 #pragma unroll
@@ -381,6 +417,12 @@ __global__ __launch_bounds__(kBlock) void k_spmm_grp(SHIRO_SPMM_PARAMS(TIN, TOUT
             if (li == LANES - 1 && ok[u]) dot_out[k + u] = q;
           }
         }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          xi[u] = xin[u];
+          v[u] = vn[u];
+          ok[u] = okn[u];
+        }
       }
       if (cvalid) {
         if (complete) {
@@ -388,15 +430,17 @@ __global__ __launch_bounds__(kBlock) void k_spmm_grp(SHIRO_SPMM_PARAMS(TIN, TOUT
           if constexpr (SCAT == 1) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) pre[e] += acc[e];
-            Elem<TOUT>::template store<VEC>(scat + (int64_t)scat_idx[r] * lds + c, pre);
+            Elem<TOUT>::template store<VEC>(scat + (int64_t)sidx * lds + c, pre);
           } else if constexpr (SCAT == 2) {
-            Elem<TOUT>::template store<VEC>(scat + (int64_t)scat_idx[r] * lds + c, acc);
+            Elem<TOUT>::template store<VEC>(scat + (int64_t)sidx * lds + c, acc);
           }
         } else {
           float* cs = carry + ((int64_t)w * 2 + (head ? 0 : 1)) * N + c;
           Elem<float>::template store<VEC>(cs, acc);
         }
       }
+      rs = rsn;
+      re = ren;
     }
   }
 }
@@ -755,14 +799,17 @@ int vec_for(int32_t N, std::initializer_list<std::pair<const void*, int64_t>> ma
   return V;
 }
 
-int grid_waves(shiro_plan plan, const shiro_tuning_t& t, int32_t W, int32_t* chunks_per_wave,
-               unsigned* blocks) {
+// Persistent grid over `workers_per_block` workers per workgroup (its
+// wavefronts, or their lane groups): at most wg_per_cu workgroups per CU,
+// each worker owning *chunks_per_worker consecutive chunks.
+int grid_waves(shiro_plan plan, const shiro_tuning_t& t, int32_t W, int32_t workers_per_block,
+               int32_t* chunks_per_worker, unsigned* blocks) {
   const int64_t max_blocks = (int64_t)plan->num_cus * (t.wg_per_cu > 0 ? t.wg_per_cu : 8);
-  int64_t nb = ceil_div(W, kWavesPerBlock);
+  int64_t nb = ceil_div(W, workers_per_block);
   if (nb > max_blocks) nb = max_blocks;
   if (nb < 1) nb = 1;
-  *chunks_per_wave = (int32_t)ceil_div(W, nb * kWavesPerBlock);
-  nb = ceil_div(ceil_div(W, *chunks_per_wave), kWavesPerBlock);
+  *chunks_per_worker = (int32_t)ceil_div(W, nb * workers_per_block);
+  nb = ceil_div(ceil_div(W, *chunks_per_worker), workers_per_block);
   if (t.xcd_remap) nb = ceil_div(nb, 8) * 8;  // whole rounds of the 8 XCDs
   *blocks = (unsigned)nb;
   return SHIRO_OK;
@@ -819,7 +866,7 @@ int run_spmm_family(shiro_plan plan, shiro_tuning_t t, const WorkList* wl, SpmmA
                     hipStream_t s) {
   t.lanes = effective_lanes(t.lanes, a.N, vec);
   unsigned nb;
-  SHIRO_TRY(grid_waves(plan, t, wl->W, &a.chunks_per_wave, &nb));
+  SHIRO_TRY(grid_waves(plan, t, wl->W, kWavesPerBlock, &a.chunks_per_wave, &nb));
   const int ntiles = (int)ceil_div(a.N, (int64_t)t.lanes * vec);
   a.xcd_remap = t.xcd_remap;
   dim3 grid(nb, ntiles);
@@ -1181,13 +1228,13 @@ int launch_sddmm(shiro_plan plan, const shiro_tuning_t& t, const float*, const v
   if (dt == SHIRO_F32) {
     const int v = vec_for<float>(N, {{dY, lddy}, {Bp, ldp}});
     tt.lanes = effective_lanes(t.lanes, N, v);
-    SHIRO_TRY(grid_waves(plan, tt, wl->W, &a.chunks_per_wave, &nb));
+    SHIRO_TRY(grid_waves(plan, tt, wl->W, kWavesPerBlock, &a.chunks_per_wave, &nb));
     if (v == 4) return sddmm_dispatch<float, 4>(tt, dim3(nb), s, a);
     return sddmm_dispatch<float, 1>(tt, dim3(nb), s, a);
   }
   const int v = vec_for<bf16_t>(N, {{dY, lddy}, {Bp, ldp}});
   tt.lanes = effective_lanes(t.lanes, N, v);
-  SHIRO_TRY(grid_waves(plan, tt, wl->W, &a.chunks_per_wave, &nb));
+  SHIRO_TRY(grid_waves(plan, tt, wl->W, kWavesPerBlock, &a.chunks_per_wave, &nb));
   if (v == 8) return sddmm_dispatch<bf16_t, 8>(tt, dim3(nb), s, a);
   return sddmm_dispatch<bf16_t, 1>(tt, dim3(nb), s, a);
 }
