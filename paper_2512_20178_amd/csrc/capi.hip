@@ -417,6 +417,8 @@ SHIRO_API int shiro_partition(int64_t n_rows, int64_t n_cols, int64_t nnz, const
       (rc = dev_alloc_n(&plan->colmap, std::max<int64_t>(plan->nnz, 1))))
     return fail(rc);
   if ((rc = launch_rebase_row_ptr(d_row_ptr + plan->row_begin, plan->rows, plan->row_ptr, s))) return fail(rc);
+  // the selection expects all-zero flags (each selection clears what it set)
+  if ((rc = launch_zero_bytes(plan->flags, plan->n_words * 32, s))) return fail(rc);
   if (plan->nnz > 0 &&
       hipMemcpyAsync(plan->col, d_col + nz0, (size_t)plan->nnz * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return fail(set_error(SHIRO_ERR_HIP, "partition: copying the panel's columns failed"));

@@ -17,10 +17,15 @@ struct WorkList {
   int32_t W = 0;
   int32_t* chunk_row = nullptr;  // W + 1
   int32_t* chunk_nz = nullptr;   // W + 1
-  // rows cut by chunk boundaries: (first chunk, last chunk, row) triples
+  // rows cut by chunk boundaries: (first chunk, last chunk, row) triples;
+  // the first nsmall have at most kFixupSmall pieces, the rest more
   int32_t nsplit = 0;
+  int32_t nsmall = 0;
   int32_t* split = nullptr;      // 3 * nsplit
 };
+
+// Split rows of at most this many pieces are summed by one lane group.
+constexpr int32_t kFixupSmall = 8;
 
 // Transposed pattern of the remapped panel: packed column u's nonzeros,
 // rows ascending.  Built by a stable radix sort of colmap.
@@ -130,6 +135,7 @@ int launch_block_nnz(const int32_t* col, int64_t nnz, int64_t K, int32_t P, int6
                      hipStream_t s);
 // Selection kernels; with sync the sizes are read back and the plan marked
 // selected, without it only the device arrays are rewritten.
+int launch_zero_bytes(uint8_t* p, int64_t n, hipStream_t s);
 int run_select(shiro_plan plan, hipStream_t s, bool sync);
 
 // ---- sort.hip ---------------------------------------------------------------

@@ -85,9 +85,19 @@ __global__ void k_block_nnz_global(const int32_t* __restrict__ col, int64_t nnz,
     atomicAdd(&out[(int64_t)col[k] / K], 1ull);
 }
 
-// flag[c] = 1 for every column id c of the panel.
+// flag[c] = 1 for every column id c of the panel.  Four ids per thread
+// (one 16-byte load when the panel's col array allows it).
 __global__ void k_mark(const int32_t* __restrict__ col, int64_t nnz, uint8_t* __restrict__ flag) {
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz;
+  const int64_t n4 = ((uintptr_t)col % 16 == 0) ? (nnz >> 2) : 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const u32x4 c = reinterpret_cast<const u32x4*>(col)[i];
+    flag[c.x] = 1;
+    flag[c.y] = 1;
+    flag[c.z] = 1;
+    flag[c.w] = 1;
+  }
+  for (int64_t k = (n4 << 2) + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz;
        k += (int64_t)gridDim.x * blockDim.x)
     flag[col[k]] = 1;
 }
@@ -107,12 +117,18 @@ __global__ void k_zero_bytes(uint8_t* __restrict__ p, int64_t n) {
 // Word table: wtab[2 w] = bits of word w (bit b = flag[32 w + b]; the flag
 // array is padded to whole words), wtab[2 w + 1] = packed position of the
 // word's first set bit.  Interleaved so that the remap reads one 8-byte entry.
-__global__ void k_fold_flags(const uint8_t* __restrict__ flag, int64_t n_words,
+// The flags read are cleared again (only the 16-byte pieces that held a 1),
+// so the array is all zero between selections; it is cleared once when the
+// plan is made.
+__global__ void k_fold_flags(uint8_t* __restrict__ flag, int64_t n_words,
                              uint32_t* __restrict__ wtab) {
+  const u32x4 zero = {0u, 0u, 0u, 0u};
   for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < n_words;
        w += (int64_t)gridDim.x * blockDim.x) {
-    const u32x4* f = reinterpret_cast<const u32x4*>(flag + (w << 5));
+    u32x4* f = reinterpret_cast<u32x4*>(flag + (w << 5));
     const u32x4 a = f[0], b = f[1];
+    if ((a.x | a.y | a.z | a.w) != 0u) f[0] = zero;
+    if ((b.x | b.y | b.z | b.w) != 0u) f[1] = zero;
     const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
     uint32_t m = 0;
 #pragma unroll
@@ -131,48 +147,83 @@ struct PopcountIn {
   __device__ int64_t operator()(int64_t w) const { return __popc(wtab[2 * w]); }
 };
 
-// Writes each word's packed offset and compacts its set bits, ascending.
-struct CompactOut {
-  uint32_t* wtab;
-  int32_t* unique_cols;
-  __device__ void operator()(int64_t w, int64_t prefix, int64_t) const {
-    wtab[2 * w + 1] = (uint32_t)prefix;
-    uint32_t bits = wtab[2 * w];
-    int32_t o = (int32_t)prefix;
-    const int32_t base = (int32_t)(w << 5);
-    while (bits) {
-      const int b = __ffs(bits) - 1;
-      unique_cols[o++] = base + b;
-      bits &= bits - 1u;
-    }
-  }
-};
+// Down pass of the selection scan.  A workgroup owns kSelItems*256 words:
+// it scans their popcounts (plus the tile offset from the tile scan), writes
+// each word's packed offset into the word table, and then compacts the
+// ids of the set bits one id per lane — lane t of the workgroup takes ids
+// t, t+256, ... of the tile, so stores of neighbouring ids are neighbours
+// and no lane walks a dense word alone.
+constexpr int kSelItems = 4;
 
-// colmap[k] = packed position of col[k] = offset of its word + set bits below it.
-__global__ void k_remap(const int32_t* __restrict__ col, int64_t nnz,
-                        const uint32_t* __restrict__ wtab, int32_t* __restrict__ colmap) {
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t c = (uint32_t)col[k];
-    const uint32_t below = (1u << (c & 31u)) - 1u;
-    const u32x2 e = reinterpret_cast<const u32x2*>(wtab)[c >> 5];
-    colmap[k] = (int32_t)e.y + __popc(e.x & below);
+__global__ __launch_bounds__(kBlock) void k_select_down(uint32_t* __restrict__ wtab, int64_t n_words,
+                                                        const int64_t* __restrict__ tile_off,
+                                                        int32_t* __restrict__ unique_cols) {
+  __shared__ int64_t lds[kWavesPerBlock];
+  __shared__ uint32_t sbits[kBlock * kSelItems];
+  __shared__ uint32_t spref[kBlock * kSelItems];
+  const int64_t tile0 = (int64_t)blockIdx.x * (kBlock * kSelItems);
+  const int64_t base = tile0 + (int64_t)threadIdx.x * kSelItems;
+  uint32_t bits[kSelItems];
+  int64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kSelItems; ++i) {
+    bits[i] = (base + i < n_words) ? wtab[2 * (base + i)] : 0u;
+    s += __popc(bits[i]);
+  }
+  int64_t ex = block_exclusive_scan<int64_t>(s, lds, nullptr) + tile_off[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kSelItems; ++i) {
+    if (base + i < n_words) wtab[2 * (base + i) + 1] = (uint32_t)ex;
+    sbits[threadIdx.x * kSelItems + i] = bits[i];
+    spref[threadIdx.x * kSelItems + i] = (uint32_t)ex;
+    ex += __popc(bits[i]);
+  }
+  __syncthreads();
+  const int32_t ids = kBlock * kSelItems * 32;
+  for (int32_t j = threadIdx.x; j < ids; j += kBlock) {
+    const int32_t lw = j >> 5;
+    const uint32_t b = (uint32_t)j & 31u;
+    const uint32_t wb = sbits[lw];
+    if ((wb >> b) & 1u) unique_cols[spref[lw] + __popc(wb & ((1u << b) - 1u))] = (int32_t)((tile0 << 5) + j);
   }
 }
 
-// block_off[q] = packed position of the first column id of block q.
-__global__ void k_block_off(const uint32_t* __restrict__ wtab,
-                            int64_t n_cols, int64_t K, int32_t P, const int64_t* __restrict__ d_U,
-                            int64_t* __restrict__ block_off) {
-  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (q > P) return;
-  int64_t c0 = q * K;
-  if (c0 >= n_cols) {
-    block_off[q] = *d_U;
-    return;
+// colmap[k] = packed position of col[k] = offset of its word + set bits
+// below it; four nonzeros per thread.  The same threads also write
+// block_off[q] = packed position of the first column id of block q (U past
+// the end) for q = 0..P.
+__global__ void k_remap(const int32_t* __restrict__ col, int64_t nnz,
+                        const uint32_t* __restrict__ wtab, int32_t* __restrict__ colmap,
+                        int64_t n_cols, int64_t K, int32_t P, const int64_t* __restrict__ d_U,
+                        int64_t* __restrict__ block_off) {
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const u32x2* tab = reinterpret_cast<const u32x2*>(wtab);
+  for (int64_t q = t0; q <= P; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c0 = q * K;
+    if (c0 >= n_cols) {
+      block_off[q] = *d_U;
+    } else {
+      const u32x2 e = tab[c0 >> 5];
+      block_off[q] = (int64_t)e.y + __popc(e.x & ((1u << ((uint32_t)c0 & 31u)) - 1u));
+    }
   }
-  const uint32_t below = (1u << ((uint32_t)c0 & 31u)) - 1u;
-  block_off[q] = (int64_t)wtab[2 * (c0 >> 5) + 1] + __popc(wtab[2 * (c0 >> 5)] & below);
+  const bool vec = ((uintptr_t)col % 16 == 0) && ((uintptr_t)colmap % 16 == 0);
+  const int64_t n4 = vec ? (nnz >> 2) : 0;
+  for (int64_t i = t0; i < n4; i += (int64_t)gridDim.x * blockDim.x) {
+    const u32x4 c = reinterpret_cast<const u32x4*>(col)[i];
+    const u32x2 e0 = tab[c.x >> 5], e1 = tab[c.y >> 5], e2 = tab[c.z >> 5], e3 = tab[c.w >> 5];
+    u32x4 o;
+    o.x = e0.y + __popc(e0.x & ((1u << (c.x & 31u)) - 1u));
+    o.y = e1.y + __popc(e1.x & ((1u << (c.y & 31u)) - 1u));
+    o.z = e2.y + __popc(e2.x & ((1u << (c.z & 31u)) - 1u));
+    o.w = e3.y + __popc(e3.x & ((1u << (c.w & 31u)) - 1u));
+    reinterpret_cast<u32x4*>(colmap)[i] = o;
+  }
+  for (int64_t k = (n4 << 2) + t0; k < nnz; k += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t c = (uint32_t)col[k];
+    const u32x2 e = tab[c >> 5];
+    colmap[k] = (int32_t)(e.y + __popc(e.x & ((1u << (c & 31u)) - 1u)));
+  }
 }
 
 unsigned grid_for(int64_t n, int64_t cap = 65536) {
@@ -216,6 +267,13 @@ int launch_block_nnz(const int32_t* col, int64_t nnz, int64_t K, int32_t P, int6
   return SHIRO_OK;
 }
 
+int launch_zero_bytes(uint8_t* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return SHIRO_OK;
+  k_zero_bytes<<<grid_for(ceil_div(n, 16), 16384), kBlock, 0, s>>>(p, n);
+  SHIRO_LAUNCH_CHECK();
+  return SHIRO_OK;
+}
+
 int run_select(shiro_plan plan, hipStream_t s, bool sync) {
   const int64_t nw = plan->n_words;
   const int64_t nnz = plan->nnz;
@@ -224,22 +282,25 @@ int run_select(shiro_plan plan, hipStream_t s, bool sync) {
   int64_t* d_U = reinterpret_cast<int64_t*>(plan->scratch);
   void* scan_tmp = reinterpret_cast<char*>(plan->scratch) + 256;
 
-  k_zero_bytes<<<grid_for(ceil_div(nw * 32, 16), 16384), kBlock, 0, s>>>(plan->flags, nw * 32);
-  SHIRO_LAUNCH_CHECK();
+  // the flag bytes are all zero here: cleared when the plan was made and
+  // by every fold since
   if (nnz > 0) {
-    k_mark<<<grid_for(nnz), kBlock, 0, s>>>(plan->col, nnz, plan->flags);
+    k_mark<<<grid_for((nnz + 3) / 4), kBlock, 0, s>>>(plan->col, nnz, plan->flags);
     SHIRO_LAUNCH_CHECK();
   }
   k_fold_flags<<<grid_for(nw), kBlock, 0, s>>>(plan->flags, nw, plan->wtab);
   SHIRO_LAUNCH_CHECK();
-  SHIRO_TRY(scan_generic<4>(PopcountIn{plan->wtab}, nw, CompactOut{plan->wtab, plan->unique_cols}, d_U,
-                         scan_tmp, s));
-  if (nnz > 0) {
-    k_remap<<<grid_for(nnz), kBlock, 0, s>>>(plan->col, nnz, plan->wtab, plan->colmap);
-    SHIRO_LAUNCH_CHECK();
-  }
-  k_block_off<<<grid_for(plan->P + 1), kBlock, 0, s>>>(plan->wtab, plan->n_cols,
-                                                        plan->K, plan->P, d_U, plan->block_off);
+  // reduce-then-scan over the word popcounts; the down pass compacts the ids
+  const int64_t ntiles = scan_tiles_of(nw, kSelItems);
+  int64_t* sums = reinterpret_cast<int64_t*>(scan_tmp);
+  k_scan_reduce<kSelItems, PopcountIn><<<dim3((unsigned)ntiles), kBlock, 0, s>>>(PopcountIn{plan->wtab}, nw, sums);
+  SHIRO_LAUNCH_CHECK();
+  k_scan_tiles<<<1, kBlock, 0, s>>>(sums, ntiles, d_U);
+  SHIRO_LAUNCH_CHECK();
+  k_select_down<<<dim3((unsigned)ntiles), kBlock, 0, s>>>(plan->wtab, nw, sums, plan->unique_cols);
+  SHIRO_LAUNCH_CHECK();
+  k_remap<<<grid_for(std::max<int64_t>((nnz + 3) / 4, (int64_t)plan->P + 1)), kBlock, 0, s>>>(
+      plan->col, nnz, plan->wtab, plan->colmap, plan->n_cols, plan->K, plan->P, d_U, plan->block_off);
   SHIRO_LAUNCH_CHECK();
   if (!sync) return SHIRO_OK;
   SHIRO_HIP(hipMemcpyAsync(plan->h_pinned, plan->block_off, (size_t)(plan->P + 1) * 8,
