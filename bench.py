@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip per-block / bf16 / parity extras")
+    ap.add_argument("--no-extras", action="store_true", help="skip the per-block, bf16, flushed, N-sweep and autograd extras")
     ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--cpu-sample-rows", type=int, default=None)
     return ap.parse_args()
@@ -146,16 +146,17 @@ def main():
             plan.replay(gid, stream=cs)
         cs.synchronize()
         torch.cuda.synchronize()  # barrier (single rank) + device sync
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         w0 = time.perf_counter()
-        e0.record(cs)
-        for _ in range(args.steps):
+        evs[0].record(cs)
+        for i in range(args.steps):
             plan.replay(gid, stream=cs)
-        e1.record(cs)
+            evs[i + 1].record(cs)
         cs.synchronize()
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
-    ms_step = e0.elapsed_time(e1) / args.steps
+    ms_step = evs[0].elapsed_time(evs[-1]) / args.steps
+    per_step = [evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)]
     flops_step = 3 * 2.0 * nnz * N
     gflops = flops_step / (ms_step * 1e-3) / 1e9
     log(f"step {ms_step * 1e3:.1f} us (wall {wall / args.steps * 1e6:.1f} us) -> {gflops:.1f} GFLOP/s")
@@ -181,19 +182,34 @@ def main():
         "spmm": lambda: shiro.spmm(plan, vals, Bp, out=Y),
         "backward": lambda: shiro.spmm_backward(plan, vals, G, Bp, dB=dB, dvals=dvals, dB_overwrite=True),
     }
-    reps = 10
-    kern_us = {}
+    reps = 20
+    kern_us, kern_stats, kern_flushed = {}, {}, {}
+    # a 1 GiB write between calls evicts L2 and the MALL (for the flushed timings)
+    scratch = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    s = torch.cuda.current_stream()
     for name, fn in ops.items():
         fn()
         torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-        s = torch.cuda.current_stream()
-        for a, b in evs:
+        evs_op = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in evs_op:
             a.record(s)
             fn()
             b.record(s)
         torch.cuda.synchronize()
-        kern_us[name] = float(np.mean([a.elapsed_time(b) for a, b in evs]) * 1e3)
+        d = np.array([a.elapsed_time(b) for a, b in evs_op]) * 1e3
+        kern_us[name] = float(d.mean())
+        kern_stats[name] = {"mean": round(float(d.mean()), 2), "median": round(float(np.median(d)), 2),
+                            "min": round(float(d.min()), 2)}
+        if not args.no_extras:
+            evs_op = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+            for a, b in evs_op:
+                scratch.fill_(1.0)
+                a.record(s)
+                fn()
+                b.record(s)
+            torch.cuda.synchronize()
+            kern_flushed[name] = round(float(np.mean([a.elapsed_time(b) for a, b in evs_op]) * 1e3), 2)
+    del scratch
     log("per-call us: " + ", ".join(f"{k}={v:.1f}" for k, v in kern_us.items()))
     alg_step = sum(alg.values())
 
@@ -230,7 +246,10 @@ def main():
                    "U": U, "N": N, "step": "select+pack_B+spmm+spmm_backward(dB rows, dvals)"},
         "roofline": roofline,
         "step_hbm_frac": round(alg_step / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "step_us_stats": {"mean": round(ms_step * 1e3, 2), "median": round(float(np.median(per_step)) * 1e3, 2),
+                          "min": round(float(np.min(per_step)) * 1e3, 2)},
         "kernels_us": {k: round(v, 2) for k, v in kern_us.items()},
+        "kernels_us_stats": kern_stats,
         "kernels_hbm_frac": {k: round(alg[k] / (kern_us[k] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) for k in kern_us},
         "algorithmic_bytes": {k: int(v) for k, v in alg.items()},
         "setup_ms": {"partition": round(t_part * 1e3, 2), "select_rows": round(t_sel * 1e3, 2)},
@@ -247,6 +266,8 @@ def main():
         dst.copy_(src)
     b.record()
     torch.cuda.synchronize()
+    if kern_flushed:
+        out["kernels_us_flushed"] = kern_flushed
     out["copy_GBs"] = round(2 * src.numel() * 4 / (a.elapsed_time(b) / (1 if args.calib_copy else 5) * 1e-3) / 1e9, 1)
     del src, dst
 
@@ -295,33 +316,67 @@ def main():
                 "backward": round(timed(lambda: shiro.spmm_backward(plan, vals, Gh, Bph, dB=dBh, dvals=dvals, dB_overwrite=True)), 2),
             }
             del Bh, Gh, Bph, Yh, dBh
-        # sampled parity of Y at full size against the FP64 oracle
-        import oracle
+        if tdt == torch.bfloat16:
+            # BF16 storage in, FP32 output
+            Y32 = torch.empty(M, N, dtype=torch.float32, device=dev)
+            out["spmm_bf16_to_f32_us"] = round(timed(lambda: shiro.spmm(plan, vals, Bp, out=Y32)), 2)
+            del Y32
+        if args.workload in ("rmat24_p128_panel0", "er24_p128_panel0") and args.N is None:
+            out["n_sweep"] = n_sweep(shiro, synth, plan, A, vals, U, M, tdt, dev, timed, args)
+        # the same layer through the autograd Function (allocates and zero-fills
+        # dB and dvals on every backward, as autograd does)
+        vp = vals.detach().clone().requires_grad_(True)
+        Bg = B.detach().clone().requires_grad_(True)
 
-        Ac = host_csr(A)
-        Bh_host = B.float().cpu().numpy()
-        rpn = Ac.row_ptr[Ac.row_begin:Ac.row_end + 1]
-        rows = np.unique(np.concatenate([np.arange(0, M, max(1, M // 256)), [int(np.argmax(np.diff(rpn)))]]))
-        yref = oracle.spmm_rows(Ac, rows, Bh_host, None)
-        den = oracle.spmm_rows(Ac, rows, Bh_host, None, abs_mode=True)
-        shiro.refresh_selection(plan)
-        shiro.spmm(plan, vals, shiro.pack_B(plan, B, out=Bp), out=Y)
-        ygot = Y.float()[torch.from_numpy(rows).to(dev)].cpu().numpy()
-        out["parity_sampled_rows"] = int(len(rows))
-        out["parity_max_rel_err"] = float(oracle.rel_err(ygot, yref, den))
-        del Bh_host
+        def autograd_step():
+            Yg = shiro.shiro_spmm(plan, vp, Bg)
+            Yg.backward(G)
+            vp.grad = None
+            Bg.grad = None
 
+        out["autograd_step_us"] = round(timed(autograd_step, n=3), 2)
+        del vp, Bg
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, B, G, N, args, out)
 
     print(json.dumps(out), flush=True)
 
 
-def host_csr(A):
-    import oracle
+def n_sweep(shiro, synth, plan, A, vals, U, M, tdt, dev, timed, args):
+    """Dense widths N = 32 .. 256 on the same panel: pack, batched spmm and
+    the per-block baseline, and the whole step (library calls, no graph)."""
+    import torch
 
-    return oracle.Csr(A.n_rows, A.n_cols, A.row_ptr.cpu().numpy(), A.col.cpu().numpy(), A.vals.cpu().numpy(),
-                      A.P, A.p)
+    res = {}
+    for n in (32, 64, 128, 256):
+        Bn = synth.dense(A.n_cols, n, 0, synth.STREAM_B, device=dev).to(tdt)
+        Gn = synth.dense(M, n, 0, synth.STREAM_DY, device=dev).to(tdt)
+        if not args.no_autotune:
+            shiro.autotune(plan, n, tdt, ops=("spmm", "backward"))
+        shiro.prepare(plan, n, tdt, ops=("spmm", "backward", "per_block"))
+        Bpn = torch.empty(U, n, dtype=tdt, device=dev)
+        Yn = torch.empty(M, n, dtype=tdt, device=dev)
+        dBn = torch.zeros(A.n_cols, n, dtype=tdt, device=dev)
+        dvn = torch.zeros(A.nnz, dtype=torch.float32, device=dev)
+
+        def stp():
+            shiro.refresh_selection(plan)
+            shiro.pack_B(plan, Bn, out=Bpn)
+            shiro.spmm(plan, vals, Bpn, out=Yn)
+            shiro.spmm_backward(plan, vals, Gn, Bpn, dB=dBn, dvals=dvn, dB_overwrite=True)
+
+        t_step = timed(stp)
+        t_b = timed(lambda: shiro.spmm(plan, vals, Bpn, out=Yn))
+        t_pb = timed(lambda: shiro.spmm(plan, vals, Bpn, out=Yn, mode="per_block"))
+        res[str(n)] = {"step_us": round(t_step, 2),
+                       "gflops": round(3 * 2.0 * int(plan.info()["nnz"]) * n / (t_step * 1e-6) / 1e9, 1),
+                       "pack_B_us": round(timed(lambda: shiro.pack_B(plan, Bn, out=Bpn)), 2),
+                       "spmm_batched_us": round(t_b, 2), "spmm_per_block_us": round(t_pb, 2),
+                       "batched_speedup": round(t_pb / t_b, 2)}
+        log(f"N={n}: {res[str(n)]}")
+        del Bn, Gn, Bpn, Yn, dBn, dvn
+        torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(A, B, G, N, args, out):
@@ -334,7 +389,8 @@ def cpu_baseline(A, B, G, N, args, out):
 
     import oracle
 
-    Ac = host_csr(A)
+    Ac = oracle.Csr(A.n_rows, A.n_cols, A.row_ptr.cpu().numpy(), A.col.cpu().numpy(), A.vals.cpu().numpy(),
+                    A.P, A.p)
     if Ac.nnz_panel > 6_000_000:
         assert A.P == 1, "row samples are taken of one-block workloads only"
         rp = Ac.row_ptr
