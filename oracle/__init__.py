@@ -59,6 +59,11 @@ def lib():
             L.oracle_spmm_t.argtypes = [_p, _p, _p, _i64, _i64, _p, _p, _i64, _i64, _p, _i64, ctypes.c_int]
             L.oracle_spmm_t_sampled.argtypes = [_p, _p, _i64, _i64, _p, _p, _p, _i64, _i64, _p, _i64, ctypes.c_int]
             L.oracle_sddmm.argtypes = [_p, _p, _i64, _i64, _p, _p, _i64, _p, _i64, _i64, _p, ctypes.c_int]
+            L.oracle_select_c_rows.argtypes = [_p, _p, _i64, _i64, _i64, _i32, _p, _p]
+            L.oracle_select_c_rows.restype = _i64
+            L.oracle_partial_c.argtypes = [_p, _p, _p, _i64, _i64, _i32, _p, _p, _p, _i64, _i64, _p, _i64,
+                                           ctypes.c_int]
+            L.oracle_aggregate_c.argtypes = [_i64, _i32, _p, _p, _p, _p, _i64, _i64, _p, _i64]
             _lib = L
     return _lib
 
@@ -225,3 +230,51 @@ def row_rel_err(Y, Yref, den) -> float:
     if np.any(num[~ok] != 0):
         return float("inf")
     return float(np.max(num[ok] / d[ok])) if np.any(ok) else 0.0
+
+
+# ----------------------------------------------------------------------------
+# row-based scheme (Sec. 3.1; Sec. 5.1 stages 3 and 5)
+# ----------------------------------------------------------------------------
+def select_c_rows(A: Csr):
+    """(row_sel int32[R], rblock_off int64[P+1]): Rows(A^(p,q)) for every block
+    q, panel-local row ids, ascending within each block, blocks back to back."""
+    nnz = A.nnz_panel
+    row_sel = np.zeros(max(nnz, 1), np.int32)
+    off = np.zeros(A.P + 1, np.int64)
+    R = lib().oracle_select_c_rows(_ptr(A.row_ptr), _ptr(A.col), A.row_begin, A.row_end, A.K, A.P,
+                                   _ptr(row_sel), _ptr(off))
+    return row_sel[:R].copy(), off
+
+
+def v_row_bytes(A: Csr, N: int, sz: int) -> np.ndarray:
+    """Sec. 3.1 Eq. V_row per block: |Rows(A^(p,q))| * N * sz."""
+    _, off = select_c_rows(A)
+    return np.diff(off) * N * sz
+
+
+def partial_c(A: Csr, B: np.ndarray, row_sel, rblock_off, abs_mode: bool = False) -> np.ndarray:
+    """Owner-side partial rows of C (R x N, float64) over B's global rows."""
+    B = _c(B, np.float32)
+    N = B.shape[1]
+    R = len(row_sel)
+    out = np.zeros((max(R, 1), N), np.float64)
+    rs = _c(row_sel if R else np.zeros(1, np.int32), np.int32)
+    lib().oracle_partial_c(_ptr(A.row_ptr), _ptr(A.col), _ptr(A.vals), A.row_begin, A.K, A.P, _ptr(rs),
+                           _ptr(_c(rblock_off, np.int64)), _ptr(B), N, N, _ptr(out), N, int(abs_mode))
+    return out[:R]
+
+
+def aggregate_c(A: Csr, Cp: np.ndarray, row_sel, rblock_off) -> np.ndarray:
+    """Receiver-side sum of partial rows into the panel's rows (M x N, float64),
+    blocks in ascending order.  Cp may be float64 or float32."""
+    N = Cp.shape[1] if Cp.ndim == 2 else 0
+    Y = np.zeros((max(A.M, 1), N), np.float64)
+    R = len(row_sel)
+    rs = _c(row_sel if R else np.zeros(1, np.int32), np.int32)
+    if Cp.dtype == np.float64:
+        cd, cf = _c(Cp if R else np.zeros((1, N)), np.float64), None
+    else:
+        cd, cf = None, _c(Cp if R else np.zeros((1, N)), np.float32)
+    lib().oracle_aggregate_c(A.M, A.P, _ptr(rs), _ptr(_c(rblock_off, np.int64)), _ptr(cd), _ptr(cf), N, N,
+                             _ptr(Y), N)
+    return Y[:A.M]

@@ -16,6 +16,10 @@
  *   - the gradients of L = <G, A B>: A^T G and the
  *     sampled products G_i . b_j at the nonzeros    (not in the paper; needed by GNN
  *                                                    training, Sec. 7.6)
+ *   - the row-based scheme: Rows(A^(p,q)) as sorted
+ *     sets, the owner's partial C rows over them,
+ *     and their sum into the panel's rows           (Table 1; Sec. 3.1 row-based scheme,
+ *                                                    Eq. V_row; Sec. 5.1 stages 3 and 5)
  * No blocking, fusion or reordering beyond the definitions.  OpenMP splits
  * independent output rows (or independent output columns for the scatter)
  * across threads; the sum for every output element is taken in ascending
@@ -248,4 +252,100 @@ void oracle_sddmm(const int64_t* row_ptr, const int32_t* col, int64_t row_begin,
       dvals[k - nz0] = s;
     }
   }
+}
+
+/* ---- Rows(A^(p,q)) for every block q (Table 1; Sec. 3.1 row-based scheme) -
+ * Rows_q is the set of panel rows (panel-local index i = global row -
+ * row_begin) holding at least one nonzero in block q, listed ascending.
+ * row_sel holds Rows_0, Rows_1, ... back to back; rblock_off is the
+ * exclusive sum of |Rows_q| (P+1 entries).  Returns R = sum_q |Rows_q|.
+ * last[q] remembers the last row added to Rows_q, so a row enters each set
+ * once whatever the order of its nonzeros.
+ */
+int64_t oracle_select_c_rows(const int64_t* row_ptr, const int32_t* col, int64_t row_begin,
+                             int64_t row_end, int64_t K, int32_t P, int32_t* row_sel,
+                             int64_t* rblock_off) {
+  int64_t* cnt = (int64_t*)calloc((size_t)P, sizeof(int64_t));
+  int64_t* last = (int64_t*)malloc((size_t)P * sizeof(int64_t));
+  for (int32_t q = 0; q < P; ++q) last[q] = -1;
+  for (int64_t g = row_begin; g < row_end; ++g)
+    for (int64_t k = row_ptr[g]; k < row_ptr[g + 1]; ++k) {
+      int64_t q = col[k] / K;
+      if (last[q] != g) {
+        last[q] = g;
+        cnt[q] += 1;
+      }
+    }
+  rblock_off[0] = 0;
+  for (int32_t q = 0; q < P; ++q) rblock_off[q + 1] = rblock_off[q] + cnt[q];
+  for (int32_t q = 0; q < P; ++q) {
+    last[q] = -1;
+    cnt[q] = rblock_off[q];
+  }
+  for (int64_t g = row_begin; g < row_end; ++g)
+    for (int64_t k = row_ptr[g]; k < row_ptr[g + 1]; ++k) {
+      int64_t q = col[k] / K;
+      if (last[q] != g) {
+        last[q] = g;
+        row_sel[cnt[q]++] = (int32_t)(g - row_begin);
+      }
+    }
+  int64_t R = rblock_off[P];
+  free(cnt);
+  free(last);
+  return R;
+}
+
+/* ---- Partial C rows computed by the owner (Sec. 3.1 row-based scheme;
+ * Sec. 5.1 stage 3: the remote computation) --------------------------------
+ * For entry e = rblock_off[q] + t (row i = Rows_q[t]):
+ *   Cp[e, j] = sum over nonzeros k of panel row i with col[k] in block q of
+ *              vals[k] * B[col[k], j],
+ * ascending k, in double.  abs_mode != 0 computes |A| |B| instead.
+ */
+void oracle_partial_c(const int64_t* row_ptr, const int32_t* col, const float* vals,
+                      int64_t row_begin, int64_t K, int32_t P, const int32_t* row_sel,
+                      const int64_t* rblock_off, const float* B, int64_t ldb, int64_t N,
+                      double* Cp, int64_t ldc, int abs_mode) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t q = 0; q < P; ++q) {
+    for (int64_t e = rblock_off[q]; e < rblock_off[q + 1]; ++e) {
+      double* c = Cp + e * ldc;
+      for (int64_t j = 0; j < N; ++j) c[j] = 0.0;
+      int64_t g = row_begin + row_sel[e];
+      for (int64_t k = row_ptr[g]; k < row_ptr[g + 1]; ++k) {
+        if (col[k] / K != q) continue;
+        double a = (double)vals[k];
+        const float* b = B + (int64_t)col[k] * ldb;
+        if (abs_mode) {
+          a = fabs(a);
+          for (int64_t j = 0; j < N; ++j) c[j] += a * fabs((double)b[j]);
+        } else {
+          for (int64_t j = 0; j < N; ++j) c[j] += a * b[j];
+        }
+      }
+    }
+  }
+}
+
+/* ---- Aggregation on the receiver (Sec. 5.1 stage 5) ----------------------
+ * Y[i, :] = sum over blocks q, ascending, of the partial row of i in block q:
+ *   Y[Rows_q[t], :] += Cp[rblock_off[q] + t, :].
+ * Rows in no Rows_q stay 0.  Y is M x N (panel rows), in double; the partial
+ * rows are given in double (Cp) or, if Cp is NULL, in float (Cpf).
+ */
+void oracle_aggregate_c(int64_t M, int32_t P, const int32_t* row_sel, const int64_t* rblock_off,
+                        const double* Cp, const float* Cpf, int64_t ldc, int64_t N, double* Y,
+                        int64_t ldy) {
+  for (int64_t i = 0; i < M; ++i)
+    for (int64_t j = 0; j < N; ++j) Y[i * ldy + j] = 0.0;
+  for (int32_t q = 0; q < P; ++q)
+    for (int64_t e = rblock_off[q]; e < rblock_off[q + 1]; ++e) {
+      double* y = Y + (int64_t)row_sel[e] * ldy;
+      if (Cp) {
+        for (int64_t j = 0; j < N; ++j) y[j] += Cp[e * ldc + j];
+      } else {
+        for (int64_t j = 0; j < N; ++j) y[j] += (double)Cpf[e * ldc + j];
+      }
+    }
 }

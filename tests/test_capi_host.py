@@ -99,3 +99,12 @@ def test_tuning_validation(lib):
 
     t = _lib.Tuning(chunk=256, lanes=64, unroll=2, group_rows=0, xcd_remap=0, wg_per_cu=8)
     assert lib.shiro_set_tuning(ctypes.c_void_p(None), 0, 128, 0, ctypes.byref(t)) == -1
+
+
+def test_set_allocator_arguments(lib):
+    from paper_2512_20178_amd import _lib
+
+    keep = _lib.ALLOC_FN(lambda n, c: None)
+    assert lib.shiro_set_allocator(keep, _lib.FREE_FN(), None) == -1
+    assert "both" in _err(lib)
+    assert lib.shiro_set_allocator(_lib.ALLOC_FN(), _lib.FREE_FN(), None) == 0  # back to hipMalloc

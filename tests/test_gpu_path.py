@@ -381,6 +381,45 @@ def test_autotune_then_correct(shiro, monkeypatch, tmp_path):
     assert len(lines) == 3 and all(ln.split()[0].endswith(("|k=0", "|k=1", "|k=2")) for ln in lines)
 
 
+def test_torch_allocator(shiro):
+    """Plan memory from torch's caching allocator: accounted by torch while the
+    plan lives, returned when it is destroyed, results unchanged."""
+    A, N = make_case("rmat12_P8_p0")
+    dev = torch.device("cuda")
+    Ad = A.to(dev)
+    B = synth.dense(A.n_cols, N, 0, synth.STREAM_B).to(dev)
+    G = None
+    Ac = oracle.Csr.from_synth(A)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    shiro.use_torch_allocator(True)
+    try:
+        plan = shiro.partition(Ad.row_ptr, Ad.col, A.n_rows, A.n_cols, A.P, A.p)
+        U, _ = shiro.select_rows(plan)
+        shiro.prepare(plan, N, torch.float32, ops=("spmm", "backward"))
+        held = torch.cuda.memory_allocated() - base
+        assert held >= 4 * Ac.nnz_panel  # at least the panel's column copy
+        Bp = shiro.pack_B(plan, B)
+        Y = shiro.spmm(plan, Ad.vals, Bp)
+        Yref = oracle.spmm(Ac, B.cpu().numpy(), None)
+        den = oracle.spmm(Ac, B.cpu().numpy(), None, abs_mode=True)
+        assert oracle.rel_err(Y.cpu().numpy(), Yref, den) <= TOL_F32
+        G = synth.dense(Ac.M, N, 0, synth.STREAM_DY).to(dev)
+        dBp = torch.empty(U, N, device=dev)
+        dvals = torch.zeros(A.nnz, device=dev)
+        shiro.spmm_backward(plan, Ad.vals, G, Bp, dBpacked=dBp, dvals=dvals)
+        uc, off, cm = oracle.select(Ac)
+        ref = oracle.spmm_t(Ac, G.cpu().numpy(), cm, n_out=len(uc))
+        rden = oracle.spmm_t(Ac, G.cpu().numpy(), cm, n_out=len(uc), abs_mode=True)
+        assert oracle.rel_err(dBp.cpu().numpy(), ref, rden) <= TOL_F32
+        plan.close()
+        del Bp, Y, G, dBp, dvals
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() == base
+    finally:
+        shiro.use_torch_allocator(False)
+
+
 def test_error_paths_on_device(shiro):
     dev = torch.device("cuda")
     # malformed CSR caught by the check mode

@@ -377,3 +377,86 @@ def test_generator_counter_hash_pinned():
     got = synth.draw_u64(key, idx)
     ref = [synth._s64(synth.mix64_py(key + (int(i) + 1) * 0x9E3779B97F4A7C15)) for i in idx]
     assert torch.equal(got, torch.tensor(ref, dtype=torch.int64))
+
+
+# ----------------------------------------------------------------------------
+# row-based scheme (Table 1 Rows; Sec. 3.1 Eq. V_row; Sec. 5.1 stages 3, 5)
+# ----------------------------------------------------------------------------
+def brute_rows(A: oracle.Csr):
+    """Rows(A^(p,q)) by testing every (panel row, block) pair for a nonzero."""
+    out = []
+    for q in range(A.P):
+        lo, hi = q * A.K, min(A.n_cols, (q + 1) * A.K)
+        rows = []
+        for i in range(A.M):
+            g = A.row_begin + i
+            cols = A.col[A.row_ptr[g]:A.row_ptr[g + 1]]
+            if np.any((cols >= lo) & (cols < hi)):
+                rows.append(i)
+        out.append(rows)
+    return out
+
+
+def test_c_rows_brute_force(case):
+    rs, off = oracle.select_c_rows(case)
+    ref = brute_rows(case)
+    assert off[0] == 0 and len(off) == case.P + 1
+    for q in range(case.P):
+        assert list(rs[off[q]:off[q + 1]]) == ref[q]
+    # R counts (row, block) pairs with a nonzero: distinct blocks per row
+    nz0, n = case.nz_begin, case.nnz_panel
+    rows = np.repeat(np.arange(case.M), np.diff(case.row_ptr[case.row_begin:case.row_end + 1]))
+    pairs = set(zip(rows.tolist(), (case.col[nz0:nz0 + n] // case.K).tolist()))
+    assert off[-1] == len(pairs)
+
+
+def test_c_rows_fig1_worked_example():
+    g = load_golden("fig1_block01.txt")
+    n, P, p = g["n"][0][0], g["P"][0][0], g["p"][0][0]
+    mask = np.zeros((n, n))
+    for r, c, v in g["nz"]:
+        mask[r, c] = v
+    Ac = oracle.Csr.from_synth(synth.from_dense_pattern(mask, P=P, p=p))
+    rs, off = oracle.select_c_rows(Ac)
+    (q, *rows), = g["expect_rows_block"]
+    assert list(rs[off[q]:off[q + 1]]) == rows
+    # Eq. V_row of Sec. 3.1: |Rows(A^(0,1))| N sz, here 3 rows (Fig. 1c)
+    assert oracle.v_row_bytes(Ac, 32, 4)[q] == 3 * 32 * 4
+
+
+def test_c_rows_one_block_is_nonempty_rows():
+    A = oracle.Csr.from_synth(synth.small_rmat(10, 8, P=1, p=0))
+    rs, off = oracle.select_c_rows(A)
+    nonempty = np.flatnonzero(np.diff(A.row_ptr[A.row_begin:A.row_end + 1]) > 0)
+    assert np.array_equal(rs, nonempty)
+
+
+def test_partial_then_aggregate_is_the_product(case):
+    rng = np.random.default_rng(11)
+    N = 6
+    B = rng.standard_normal((case.n_cols, N)).astype(np.float32)
+    rs, off = oracle.select_c_rows(case)
+    Cp = oracle.partial_c(case, B, rs, off)
+    assert Cp.shape == (off[-1], N)
+    Y = oracle.aggregate_c(case, Cp, rs, off)
+    D = dense_of(case)[case.row_begin:case.row_end]
+    assert np.allclose(Y, D @ B.astype(np.float64), rtol=1e-12, atol=1e-12)
+    # each partial row is the block's own slice of the product
+    for q in range(case.P):
+        lo, hi = q * case.K, min(case.n_cols, (q + 1) * case.K)
+        ref = D[:, lo:hi] @ B[lo:hi].astype(np.float64)
+        assert np.allclose(Cp[off[q]:off[q + 1]], ref[rs[off[q]:off[q + 1]]], rtol=1e-12, atol=1e-12)
+    # the absolute-value form gives |A| |B|
+    Ya = oracle.aggregate_c(case, oracle.partial_c(case, B, rs, off, abs_mode=True), rs, off)
+    assert np.allclose(Ya, np.abs(D) @ np.abs(B.astype(np.float64)), rtol=1e-12, atol=1e-12)
+
+
+def test_aggregate_is_indexed_add():
+    A = oracle.Csr.from_synth(synth.small_rmat(9, 8, P=4, p=1))
+    rs, off = oracle.select_c_rows(A)
+    rng = np.random.default_rng(5)
+    Cp = rng.integers(-8, 9, size=(len(rs), 3)).astype(np.float32)  # exact in any order
+    Y = oracle.aggregate_c(A, Cp, rs, off)
+    ref = np.zeros((A.M, 3))
+    np.add.at(ref, rs, Cp.astype(np.float64))
+    assert np.array_equal(Y, ref)
