@@ -316,6 +316,23 @@ def main():
                 "backward": round(timed(lambda: shiro.spmm_backward(plan, vals, Gh, Bph, dB=dBh, dvals=dvals, dB_overwrite=True)), 2),
             }
             del Bh, Gh, Bph, Yh, dBh
+        # the row-based scheme on the same panel: Rows(A^(p,q)) per block, the
+        # owner's partial C rows and their sum into the panel (volumes of
+        # Sec. 3.1 Eq. V_row against Eq. V_col; off-diagonal blocks apart,
+        # since the paper uses local rows for the diagonal block)
+        t = time.perf_counter()
+        R, Rq = shiro.select_c_rows(plan)
+        t_rsel = time.perf_counter() - t
+        shiro.prepare(plan, N, tdt, ops=("row_based",))
+        Cp = torch.empty(R, N, dtype=tdt, device=dev)
+        t_pc = timed(lambda: shiro.partial_c(plan, vals, B, R, out=Cp))
+        t_ag = timed(lambda: shiro.aggregate_c(plan, Cp, out=Y))
+        out["row_based"] = {"R": R, "U": U, "R_offdiag": R - Rq[A.p], "U_offdiag": U - Uq[A.p],
+                            "v_row_bytes": R * N * sz, "v_col_bytes": U * N * sz,
+                            "setup_ms": round(t_rsel * 1e3, 2), "partial_c_us": round(t_pc, 2),
+                            "aggregate_c_us": round(t_ag, 2), "forward_us": round(t_pc + t_ag, 2)}
+        log(f"row-based: {out['row_based']}")
+        del Cp
         if tdt == torch.bfloat16:
             # BF16 storage in, FP32 output
             Y32 = torch.empty(M, N, dtype=torch.float32, device=dev)

@@ -53,6 +53,7 @@
 #ifndef SHIRO_H
 #define SHIRO_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -74,6 +75,13 @@ typedef struct ihipStream_t* shiro_stream_t;
  * pattern is unchanged (the paper reuses its offline analysis the same way,
  * Sec. 5.1 and Sec. 5.3). */
 typedef struct shiro_plan_s* shiro_plan;
+
+/* Caller-supplied device allocator (e.g. a framework's caching allocator).
+ * alloc returns device memory of at least `bytes` bytes, aligned to 256
+ * bytes, on the current device, or NULL; free receives the pointer and the
+ * size it was allocated with. */
+typedef void* (*shiro_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*shiro_free_fn)(void* ptr, size_t bytes, void* ctx);
 
 typedef enum {
   SHIRO_F32 = 0,  /* IEEE binary32 */
@@ -105,6 +113,7 @@ enum {
 #define SHIRO_OP_SPMM 1u
 #define SHIRO_OP_BACKWARD 2u
 #define SHIRO_OP_PER_BLOCK 4u
+#define SHIRO_OP_ROW_BASED 8u
 
 typedef struct {
   int64_t n_rows, n_cols; /* global matrix shape                              */
@@ -236,6 +245,46 @@ SHIRO_API int shiro_spmm_backward(shiro_plan plan, const float* d_vals, const vo
                                   int64_t lddb, float* d_dvals, uint32_t flags,
                                   shiro_stream_t stream);
 
+/* ---- Row-based scheme (Table 1 Rows; Sec. 3.1 row-based scheme, Eq. V_row;
+ * Sec. 5.1 stage 3 remote computation, stage 5 aggregation) -------------
+ * Rows(A^(p,q)) is the set of panel rows with a nonzero in column block q.
+ * The owner q of B^(q,:) computes the partial rows
+ *   Cp[e, :] = sum_{k in row Rows_q[t] of block q} vals[k] * B[col[k], :]
+ * for entry e = rblock_off[q] + t, and the receiver sums them into its rows
+ *   Y[i, :] = sum over blocks q (ascending) of the entry of row i in block q.
+ * On one GPU both sides run on the same device, with B given in full.
+ *
+ * shiro_select_c_rows builds the row-based structures (setup: allocates and
+ * synchronises) and returns R = sum_q |Rows(A^(p,q))| in *h_R and, when
+ * h_R_per_block is not NULL, |Rows(A^(p,q))| for q = 0..P-1. */
+SHIRO_API int shiro_select_c_rows(shiro_plan plan, shiro_stream_t stream, int64_t* h_R,
+                                  int64_t* h_R_per_block);
+
+/* Copy Rows_0, Rows_1, ... (panel-local row ids, ascending within a block;
+ * d_rows int32[R]) and rblock_off (d_rblock_off int64[P+1]) into
+ * caller-owned device buffers (either may be NULL).  NOT_READY before
+ * shiro_select_c_rows. */
+SHIRO_API int shiro_copy_c_row_selection(shiro_plan plan, int32_t* d_rows, int64_t* d_rblock_off,
+                                         shiro_stream_t stream);
+
+/* The owner's partial rows: d_Cp (R x N, leading dimension ldc, out_dt)
+ * overwritten from d_B (n_cols x N, ldb, in_dt; global rows) and d_vals
+ * (float32, indexed like shiro_partition's d_col).  Float32 arithmetic, each
+ * entry rounded once.  Pairs: F32->F32, BF16->F32, BF16->BF16.  NOT_READY
+ * before shiro_select_c_rows; CAPTURING if capture is active and the
+ * structures for (N, dtype) were not prepared (SHIRO_OP_ROW_BASED). */
+SHIRO_API int shiro_partial_c(shiro_plan plan, const float* d_vals, const void* d_B, int64_t ldb,
+                              int32_t N, shiro_dtype in_dt, void* d_Cp, int64_t ldc,
+                              shiro_dtype out_dt, shiro_stream_t stream);
+
+/* The receiver's sum: d_Y (rows x N, ldy, out_dt) overwritten with the sum
+ * of each panel row's partial rows from d_Cp (R x N, ldc, in_dt), blocks in
+ * ascending order; rows with no entry get 0.  Same pairs and errors as
+ * shiro_partial_c. */
+SHIRO_API int shiro_aggregate_c(shiro_plan plan, const void* d_Cp, int64_t ldc, int32_t N,
+                                shiro_dtype in_dt, void* d_Y, int64_t ldy, shiro_dtype out_dt,
+                                shiro_stream_t stream);
+
 /* Build everything the per-call steps need for (N, dtype, ops) - work lists,
  * transposed pattern, carry buffers - so later calls neither allocate nor
  * synchronise (required before graph capture).  Synchronises the stream. */
@@ -266,6 +315,15 @@ SHIRO_API int shiro_set_tuning(shiro_plan plan, int32_t kernel, int32_t N, shiro
 SHIRO_API int shiro_graph_begin(shiro_plan plan, shiro_stream_t stream);
 SHIRO_API int shiro_graph_end(shiro_plan plan, shiro_stream_t stream, int32_t* h_graph_id);
 SHIRO_API int shiro_graph_launch(shiro_plan plan, int32_t graph_id, shiro_stream_t stream);
+
+/* Route the library's own device allocations (plan arrays, work lists,
+ * carry and scratch buffers, autotuner buffers) through alloc/free instead
+ * of hipMalloc/hipFree, so the caller's allocator owns all memory; both
+ * NULL restores hipMalloc.  Process-wide; affects later allocations only
+ * (each block is released through the allocator that made it).  One of the
+ * two NULL: INVALID_ARG.  Allocation failures surface as OOM from the call
+ * that allocates. */
+SHIRO_API int shiro_set_allocator(shiro_alloc_fn alloc, shiro_free_fn free_fn, void* ctx);
 
 /* Release the plan and everything it owns (synchronises the device first).
  * NULL is accepted. */

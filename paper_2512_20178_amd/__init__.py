@@ -28,12 +28,17 @@ __all__ = [
     "pack_B",
     "spmm",
     "spmm_backward",
+    "select_c_rows",
+    "c_row_selection",
+    "partial_c",
+    "aggregate_c",
     "prepare",
     "autotune",
     "get_tuning",
     "set_tuning",
     "ShiroSpMM",
     "shiro_spmm",
+    "use_torch_allocator",
     "version",
 ]
 
@@ -43,6 +48,36 @@ _KERNELS = {"spmm": _lib.KERNEL_SPMM, "spmm_t": _lib.KERNEL_SPMM_T, "sddmm": _li
 
 def _L():
     return _lib.load()
+
+
+# ---------------------------------------------------------------------------
+# allocator hook: the library's device memory from torch's caching allocator
+# ---------------------------------------------------------------------------
+_alloc_hooks = None  # keeps the ctypes callbacks alive while installed
+
+
+def use_torch_allocator(enable: bool = True) -> None:
+    """Route the library's own device allocations through torch's caching
+    allocator (so torch.cuda.memory_allocated() accounts for plans), or back
+    to hipMalloc with enable=False.  Affects allocations made afterwards."""
+    global _alloc_hooks
+    if not enable:
+        _lib.check(_L().shiro_set_allocator(_lib.ALLOC_FN(), _lib.FREE_FN(), None))
+        _alloc_hooks = None
+        return
+
+    def _alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except RuntimeError:
+            return None
+
+    def _free(ptr, nbytes, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    hooks = (_lib.ALLOC_FN(_alloc), _lib.FREE_FN(_free))
+    _lib.check(_L().shiro_set_allocator(hooks[0], hooks[1], None))
+    _alloc_hooks = hooks
 
 
 def _stream(stream=None) -> int:
@@ -61,8 +96,12 @@ def _ptr(t: Optional[torch.Tensor]):
 
 
 def _ld(t: torch.Tensor) -> int:
-    if t.dim() != 2 or t.stride(1) != 1:
-        raise ValueError("dense operands must be 2-D with unit column stride (row-major)")
+    if t.dim() != 2:
+        raise ValueError("dense operands must be 2-D")
+    if t.numel() == 0:  # an empty operand has no meaningful strides
+        return max(t.shape[1], 1)
+    if t.stride(1) != 1 or t.stride(0) < t.shape[1]:
+        raise ValueError("dense operands must be row-major with unit column stride")
     return t.stride(0)
 
 
@@ -231,7 +270,51 @@ def spmm_backward(plan: Plan, vals: torch.Tensor, dY: torch.Tensor, Bpacked: Opt
     return dBpacked, dB, dvals
 
 
-_OPS = {"spmm": _lib.OP_SPMM, "backward": _lib.OP_BACKWARD, "per_block": _lib.OP_PER_BLOCK}
+# ---------------------------------------------------------------------------
+# row-based scheme: owner-side partial C rows and their sum into the panel
+# ---------------------------------------------------------------------------
+def select_c_rows(plan: Plan, stream=None) -> Tuple[int, list]:
+    """Build Rows(A^(p,q)) for every block; returns (R, [|Rows_q|])."""
+    R = ctypes.c_int64()
+    per = (ctypes.c_int64 * max(plan.P, 1))()
+    _lib.check(_L().shiro_select_c_rows(plan.handle, ctypes.c_void_p(_stream(stream)), ctypes.byref(R), per))
+    return R.value, list(per[:plan.P])
+
+
+def c_row_selection(plan: Plan, R: int, stream=None):
+    """(rows int32[R], rblock_off int64[P+1]) on the plan's device."""
+    rows = torch.empty(max(R, 1), dtype=torch.int32, device=plan.device)
+    off = torch.empty(plan.P + 1, dtype=torch.int64, device=plan.device)
+    _lib.check(_L().shiro_copy_c_row_selection(plan.handle, _ptr(rows), _ptr(off), ctypes.c_void_p(_stream(stream))))
+    return rows[:R], off
+
+
+def partial_c(plan: Plan, vals: torch.Tensor, B: torch.Tensor, R: int, out: Optional[torch.Tensor] = None,
+              out_dtype=None, stream=None) -> torch.Tensor:
+    """Cp[e] = sum over block q's nonzeros of row Rows_q[t] of vals[k] * B[col[k]] (R x N)."""
+    _dev(B)
+    N = B.shape[1]
+    if out is None:
+        out = torch.empty(R, N, dtype=out_dtype or B.dtype, device=B.device)
+    _lib.check(_L().shiro_partial_c(plan.handle, _ptr(vals), _ptr(B), _ld(B), N, _dt(B.dtype), _ptr(out), _ld(out),
+                                    _dt(out.dtype), ctypes.c_void_p(_stream(stream))))
+    return out
+
+
+def aggregate_c(plan: Plan, Cp: torch.Tensor, out: Optional[torch.Tensor] = None, out_dtype=None,
+                stream=None) -> torch.Tensor:
+    """Y[i] = sum over blocks (ascending) of row i's partial rows (rows x N)."""
+    _dev(Cp)
+    N = Cp.shape[1]
+    if out is None:
+        out = torch.empty(plan.rows, N, dtype=out_dtype or Cp.dtype, device=Cp.device)
+    _lib.check(_L().shiro_aggregate_c(plan.handle, _ptr(Cp), _ld(Cp), N, _dt(Cp.dtype), _ptr(out), _ld(out),
+                                      _dt(out.dtype), ctypes.c_void_p(_stream(stream))))
+    return out
+
+
+_OPS = {"spmm": _lib.OP_SPMM, "backward": _lib.OP_BACKWARD, "per_block": _lib.OP_PER_BLOCK,
+        "row_based": _lib.OP_ROW_BASED}
 
 
 def _ops(ops) -> int:

@@ -36,6 +36,7 @@ DB_OVERWRITE = 1
 OP_SPMM = 1
 OP_BACKWARD = 2
 OP_PER_BLOCK = 4
+OP_ROW_BASED = 8
 
 KERNEL_SPMM = 0
 KERNEL_SPMM_T = 1
@@ -57,6 +58,10 @@ EXPORTS = [
     "shiro_pack_B",
     "shiro_spmm",
     "shiro_spmm_backward",
+    "shiro_select_c_rows",
+    "shiro_copy_c_row_selection",
+    "shiro_partial_c",
+    "shiro_aggregate_c",
     "shiro_prepare",
     "shiro_autotune",
     "shiro_get_tuning",
@@ -64,8 +69,13 @@ EXPORTS = [
     "shiro_graph_begin",
     "shiro_graph_end",
     "shiro_graph_launch",
+    "shiro_set_allocator",
     "shiro_plan_destroy",
 ]
+
+# shiro_alloc_fn / shiro_free_fn
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 
 
 class ShiroError(RuntimeError):
@@ -136,6 +146,10 @@ def load(path: str = LIB_PATH):
         L.shiro_spmm.argtypes = [_p, _p, _p, _i64, _i32, ctypes.c_int, _p, _i64, ctypes.c_int, _u32, _p]
         L.shiro_spmm_backward.argtypes = [_p, _p, _p, _i64, _p, _i64, _i32, ctypes.c_int, _p, _i64, _p, _i64, _p,
                                           ctypes.c_uint32, _p]
+        L.shiro_select_c_rows.argtypes = [_p, _p, ctypes.POINTER(_i64), _p]
+        L.shiro_copy_c_row_selection.argtypes = [_p, _p, _p, _p]
+        L.shiro_partial_c.argtypes = [_p, _p, _p, _i64, _i32, ctypes.c_int, _p, _i64, ctypes.c_int, _p]
+        L.shiro_aggregate_c.argtypes = [_p, _p, _i64, _i32, ctypes.c_int, _p, _i64, ctypes.c_int, _p]
         L.shiro_prepare.argtypes = [_p, _i32, ctypes.c_int, _u32, _p]
         L.shiro_autotune.argtypes = [_p, _i32, ctypes.c_int, _u32, _p]
         L.shiro_get_tuning.argtypes = [_p, _i32, _i32, ctypes.c_int, ctypes.POINTER(Tuning)]
@@ -143,6 +157,7 @@ def load(path: str = LIB_PATH):
         L.shiro_graph_begin.argtypes = [_p, _p]
         L.shiro_graph_end.argtypes = [_p, _p, ctypes.POINTER(_i32)]
         L.shiro_graph_launch.argtypes = [_p, _i32, _p]
+        L.shiro_set_allocator.argtypes = [ALLOC_FN, FREE_FN, _p]
         L.shiro_plan_destroy.argtypes = [_p]
         for name in EXPORTS:
             if name != "shiro_last_error":

@@ -5,8 +5,10 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "plan.hpp"
@@ -20,22 +22,82 @@ int set_error(int code, const std::string& msg) {
   return code;
 }
 
+// Device memory of plans and tuning buffers: hipMalloc, or the caller's
+// allocator after shiro_set_allocator.  Every block remembers the allocator
+// that made it, so it is returned to that one even if the hook changes.
+namespace {
+struct Allocator {
+  shiro_alloc_fn alloc = nullptr;
+  shiro_free_fn free = nullptr;
+  void* ctx = nullptr;
+};
+struct Block {
+  Allocator by;
+  int64_t bytes;
+};
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+std::unordered_map<void*, Block> g_blocks;
+}  // namespace
+
+int set_allocator(shiro_alloc_fn alloc, shiro_free_fn free, void* ctx) {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc = Allocator{alloc, free, ctx};
+  return SHIRO_OK;
+}
+
 int dev_alloc(void** p, int64_t bytes) {
   *p = nullptr;
   if (bytes <= 0) bytes = 1;
-  hipError_t e = hipMalloc(p, (size_t)bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    *p = nullptr;
-    return set_error(e == hipErrorOutOfMemory ? SHIRO_ERR_OOM : SHIRO_ERR_HIP,
-                     "device allocation of " + std::to_string(bytes) + " bytes failed: " +
-                         hipGetErrorString(e));
+  Allocator a;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    a = g_alloc;
   }
+  if (a.alloc) {
+    *p = a.alloc((size_t)bytes, a.ctx);
+    if (!*p)
+      return set_error(SHIRO_ERR_OOM, "device allocation of " + std::to_string(bytes) +
+                                          " bytes failed (caller's allocator returned NULL)");
+    if ((uintptr_t)*p % 256 != 0) {
+      a.free(*p, (size_t)bytes, a.ctx);
+      *p = nullptr;
+      return set_error(SHIRO_ERR_UNSUPPORTED, "caller's allocator returned memory not aligned to 256 bytes");
+    }
+  } else {
+    hipError_t e = hipMalloc(p, (size_t)bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      return set_error(e == hipErrorOutOfMemory ? SHIRO_ERR_OOM : SHIRO_ERR_HIP,
+                       "device allocation of " + std::to_string(bytes) + " bytes failed: " +
+                           hipGetErrorString(e));
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_blocks[*p] = Block{a, bytes};
   return SHIRO_OK;
 }
 
 void dev_free(void* p) {
-  if (p) (void)hipFree(p);
+  if (!p) return;
+  Block b{};
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    auto it = g_blocks.find(p);
+    if (it != g_blocks.end()) {
+      b = it->second;
+      g_blocks.erase(it);
+    }
+  }
+  if (b.by.free) {
+    // a caller's allocator may hand the block out again at once (hipFree
+    // would wait for the device), so nothing of ours may still be using it
+    (void)hipDeviceSynchronize();
+    b.by.free(p, (size_t)b.bytes, b.by.ctx);
+  } else {
+    (void)hipFree(p);
+  }
 }
 
 bool stream_capturing(hipStream_t s) {
@@ -67,6 +129,25 @@ int ensure_rows_work(shiro_plan plan, int32_t chunk, bool allocate, hipStream_t 
     it = plan->rows_work.emplace(chunk, wl).first;
   }
   *out = &it->second;
+  return SHIRO_OK;
+}
+
+int ensure_rb_work(shiro_plan plan, int32_t chunk, bool allocate, hipStream_t s,
+                   const WorkList** rb, const WorkList** agg) {
+  for (int which = 0; which < 2; ++which) {
+    auto& m = which == 0 ? plan->rb_work : plan->agg_work;
+    auto it = m.find(chunk);
+    if (it == m.end()) {
+      if (!allocate)
+        return set_error(SHIRO_ERR_CAPTURING,
+                         "row-based work list for chunk " + std::to_string(chunk) + " not prepared before capture");
+      WorkList wl;
+      if (which == 0) SHIRO_TRY(build_worklist(plan->rb.ptr, plan->rb.R, plan->nnz, chunk, &wl, s));
+      else SHIRO_TRY(build_worklist(plan->rb.agg_ptr, plan->rows, plan->rb.R, chunk, &wl, s));
+      it = m.emplace(chunk, wl).first;
+    }
+    *(which == 0 ? rb : agg) = &it->second;
+  }
   return SHIRO_OK;
 }
 
@@ -171,7 +252,7 @@ static void plan_free(shiro_plan plan) {
   dev_free(plan->unique_cols);
   dev_free(plan->block_off);
   dev_free(plan->colmap);
-  for (auto* m : {&plan->rows_work, &plan->cols_work})
+  for (auto* m : {&plan->rows_work, &plan->cols_work, &plan->rb_work, &plan->agg_work})
     for (auto& kv : *m) {
       dev_free(kv.second.chunk_row);
       dev_free(kv.second.chunk_nz);
@@ -185,6 +266,15 @@ static void plan_free(shiro_plan plan) {
   dev_free(plan->seg.seg_row);
   dev_free(plan->seg.seg_begin);
   dev_free(plan->seg.seg_end);
+  dev_free(plan->seg.seg_csr);
+  dev_free(plan->rb.ptr);
+  dev_free(plan->rb.col);
+  dev_free(plan->rb.perm);
+  dev_free(plan->rb.agg_ptr);
+  dev_free(plan->rb.agg_idx);
+  dev_free(plan->rb.ones);
+  dev_free(plan->rb.vals);
+  dev_free(plan->rb.block_off);
   dev_free(plan->carry);
   dev_free(plan->acc32);
   dev_free(plan->scratch);
@@ -575,6 +665,65 @@ SHIRO_API int shiro_spmm_backward(shiro_plan plan, const float* d_vals, const vo
   return SHIRO_OK;
 }
 
+SHIRO_API int shiro_select_c_rows(shiro_plan plan, shiro_stream_t stream, int64_t* h_R,
+                                  int64_t* h_R_per_block) {
+  if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "select_c_rows: plan is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (stream_capturing(s)) return set_error(SHIRO_ERR_CAPTURING, "select_c_rows: stream is capturing");
+  SHIRO_TRY(build_rowbased(plan, s));
+  if (h_R) *h_R = plan->rb.R;
+  if (h_R_per_block)
+    for (int32_t q = 0; q < plan->P; ++q) h_R_per_block[q] = plan->seg.h_off[q + 1] - plan->seg.h_off[q];
+  return SHIRO_OK;
+}
+
+SHIRO_API int shiro_copy_c_row_selection(shiro_plan plan, int32_t* d_rows, int64_t* d_rblock_off,
+                                         shiro_stream_t stream) {
+  if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "copy_c_row_selection: plan is NULL");
+  if (!plan->rb.built) return set_error(SHIRO_ERR_NOT_READY, "copy_c_row_selection: call shiro_select_c_rows first");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (d_rows && plan->rb.R > 0)
+    SHIRO_HIP(hipMemcpyAsync(d_rows, plan->seg.seg_row, (size_t)plan->rb.R * 4, hipMemcpyDeviceToDevice, s));
+  if (d_rblock_off)
+    SHIRO_HIP(hipMemcpyAsync(d_rblock_off, plan->rb.block_off, (size_t)(plan->P + 1) * 8,
+                             hipMemcpyDeviceToDevice, s));
+  return SHIRO_OK;
+}
+
+static bool valid_pair(shiro_dtype in_dt, shiro_dtype out_dt) {
+  return (in_dt == SHIRO_F32 && out_dt == SHIRO_F32) || (in_dt == SHIRO_BF16 && out_dt == SHIRO_F32) ||
+         (in_dt == SHIRO_BF16 && out_dt == SHIRO_BF16);
+}
+
+SHIRO_API int shiro_partial_c(shiro_plan plan, const float* d_vals, const void* d_B, int64_t ldb, int32_t N,
+                              shiro_dtype in_dt, void* d_Cp, int64_t ldc, shiro_dtype out_dt,
+                              shiro_stream_t stream) {
+  if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "partial_c: plan is NULL");
+  if (!plan->rb.built) return set_error(SHIRO_ERR_NOT_READY, "partial_c: call shiro_select_c_rows first");
+  if (!valid_pair(in_dt, out_dt))
+    return set_error(SHIRO_ERR_UNSUPPORTED, "partial_c: dtype pair not supported (F32->F32, BF16->F32, BF16->BF16)");
+  if (N < 0 || ldb < N || ldc < N) return set_error(SHIRO_ERR_INVALID_ARG, "partial_c: need N >= 0, ldb >= N, ldc >= N");
+  if (N > 0 && plan->rb.R > 0 && (!d_vals || !d_B || !d_Cp))
+    return set_error(SHIRO_ERR_INVALID_ARG, "partial_c: NULL pointer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return launch_partial_c(plan, tuning_for(plan, SHIRO_KERNEL_SPMM, N, in_dt), d_vals, d_B, ldb, N, in_dt, d_Cp,
+                          ldc, out_dt, s);
+}
+
+SHIRO_API int shiro_aggregate_c(shiro_plan plan, const void* d_Cp, int64_t ldc, int32_t N, shiro_dtype in_dt,
+                                void* d_Y, int64_t ldy, shiro_dtype out_dt, shiro_stream_t stream) {
+  if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "aggregate_c: plan is NULL");
+  if (!plan->rb.built) return set_error(SHIRO_ERR_NOT_READY, "aggregate_c: call shiro_select_c_rows first");
+  if (!valid_pair(in_dt, out_dt))
+    return set_error(SHIRO_ERR_UNSUPPORTED, "aggregate_c: dtype pair not supported (F32->F32, BF16->F32, BF16->BF16)");
+  if (N < 0 || ldc < N || ldy < N) return set_error(SHIRO_ERR_INVALID_ARG, "aggregate_c: need N >= 0, ldc >= N, ldy >= N");
+  if (N > 0 && plan->rows > 0 && (!d_Y || (plan->rb.R > 0 && !d_Cp)))
+    return set_error(SHIRO_ERR_INVALID_ARG, "aggregate_c: NULL pointer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return launch_aggregate_c(plan, tuning_for(plan, SHIRO_KERNEL_SPMM, N, in_dt), d_Cp, ldc, N, in_dt, d_Y, ldy,
+                            out_dt, s);
+}
+
 SHIRO_API int shiro_prepare(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t ops,
                             shiro_stream_t stream) {
   if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "prepare: plan is NULL");
@@ -596,6 +745,13 @@ SHIRO_API int shiro_prepare(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t
     SHIRO_TRY(ensure_carry(plan, (int64_t)wl->W * 2 * N, true));
     const shiro_tuning_t t2 = tuning_for(plan, SHIRO_KERNEL_SDDMM, N, dt);
     SHIRO_TRY(ensure_rows_work(plan, t2.chunk, true, s, &wl));
+  }
+  if (ops & SHIRO_OP_ROW_BASED) {
+    SHIRO_TRY(build_rowbased(plan, s));
+    const shiro_tuning_t t = tuning_for(plan, SHIRO_KERNEL_SPMM, N, dt);
+    const WorkList *wr, *wa;
+    SHIRO_TRY(ensure_rb_work(plan, t.chunk, true, s, &wr, &wa));
+    SHIRO_TRY(ensure_carry(plan, (int64_t)std::max(wr->W, wa->W) * 2 * N, true));
   }
   if (ops & SHIRO_OP_PER_BLOCK) {
     SHIRO_TRY(build_segments(plan, s));
@@ -686,6 +842,12 @@ SHIRO_API int shiro_graph_launch(shiro_plan plan, int32_t graph_id, shiro_stream
     return set_error(SHIRO_ERR_INVALID_ARG, "graph_launch: unknown graph id");
   SHIRO_HIP(hipGraphLaunch(plan->graphs[graph_id], reinterpret_cast<hipStream_t>(stream)));
   return SHIRO_OK;
+}
+
+SHIRO_API int shiro_set_allocator(shiro_alloc_fn alloc, shiro_free_fn free_fn, void* ctx) {
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return set_error(SHIRO_ERR_INVALID_ARG, "set_allocator: give both functions or neither");
+  return set_allocator(alloc, free_fn, ctx);
 }
 
 SHIRO_API int shiro_plan_destroy(shiro_plan plan) {

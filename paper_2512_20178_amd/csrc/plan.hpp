@@ -43,7 +43,26 @@ struct BlockSegments {
   int32_t* seg_row = nullptr;    // nseg
   int32_t* seg_begin = nullptr;  // nseg (CSR positions)
   int32_t* seg_end = nullptr;    // nseg
+  int32_t* seg_csr = nullptr;    // nseg: index of the segment in CSR (row, block) order
   std::vector<int64_t> h_off;    // P + 1 (host copy: launch sizes)
+};
+
+// Row-based scheme (Sec. 3.1): the (row, block) segments in block-major
+// order are the entries of Rows(A^(p,q)) for q = 0, 1, ...  The owner's
+// partial rows are an SpMM over the segments gathering B rows by global
+// column id; the receiver's sum is an SpMM of the panel rows over the
+// entries with unit weights, blocks ascending.
+struct RowBased {
+  bool built = false;
+  int64_t R = 0;
+  int64_t* ptr = nullptr;       // R + 1: each entry's nonzeros in the block-major copy
+  int32_t* col = nullptr;       // nnz: global column id of each nonzero, block-major
+  int32_t* perm = nullptr;      // nnz: CSR position of each nonzero, block-major
+  int64_t* agg_ptr = nullptr;   // rows + 1: each panel row's entries
+  int32_t* agg_idx = nullptr;   // R: entry position of each (row, block) pair, blocks ascending
+  float* ones = nullptr;        // R: unit weights of the sum
+  float* vals = nullptr;        // nnz: values in block-major order (per call)
+  int64_t* block_off = nullptr; // P + 1: first entry of each block
 };
 
 struct TuneKey {
@@ -82,6 +101,9 @@ struct shiro_plan_s {
   std::map<int32_t, shiro::WorkList> cols_work;   // keyed by chunk size (transposed pattern)
   shiro::Transposed tr;
   shiro::BlockSegments seg;
+  shiro::RowBased rb;
+  std::map<int32_t, shiro::WorkList> rb_work;   // keyed by chunk size (partial C rows)
+  std::map<int32_t, shiro::WorkList> agg_work;  // keyed by chunk size (sum into the panel)
 
   // carry slots of split rows: 2 * W * carry_cols floats
   float* carry = nullptr;
@@ -150,6 +172,17 @@ int build_worklist(const int64_t* ptr, int64_t R, int64_t nnz, int32_t chunk, Wo
                    hipStream_t s);
 int build_transposed(shiro_plan plan, hipStream_t s);
 int build_segments(shiro_plan plan, hipStream_t s);
+int build_rowbased(shiro_plan plan, hipStream_t s);
+// Row-based scheme: the owner's partial C rows over B (global rows), and
+// their sum into the panel's rows.
+int launch_partial_c(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* B,
+                     int64_t ldb, int32_t N, shiro_dtype in_dt, void* Cp, int64_t ldc,
+                     shiro_dtype out_dt, hipStream_t s);
+int launch_aggregate_c(shiro_plan plan, const shiro_tuning_t& t, const void* Cp, int64_t ldc,
+                       int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy, shiro_dtype out_dt,
+                       hipStream_t s);
+int ensure_rb_work(shiro_plan plan, int32_t chunk, bool allocate, hipStream_t s,
+                   const WorkList** rb, const WorkList** agg);
 
 int launch_pack(shiro_plan plan, const void* B, int64_t ldb, int32_t N, shiro_dtype dt,
                 void* Bp, int64_t ldp, hipStream_t s);

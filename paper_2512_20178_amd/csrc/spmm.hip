@@ -826,6 +826,64 @@ unsigned grid_for(int64_t n, int64_t cap = 65536) {
 }
 
 // ---------------------------------------------------------------------------
+// row-based scheme: setup of the block-major copy and of the sum pattern
+// ---------------------------------------------------------------------------
+// For nonzero t of the block-major order: its entry j (ptr[j] <= t <
+// ptr[j+1]), its CSR position and its global column id.
+__global__ void k_rb_fill(const int64_t* __restrict__ ptr, int64_t R, const int32_t* __restrict__ seg_begin,
+                          const int32_t* __restrict__ col, int64_t nnz, int32_t* __restrict__ perm,
+                          int32_t* __restrict__ col_bm) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nnz;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = R - 1;  // last j with ptr[j] <= t
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (ptr[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const int32_t k = seg_begin[lo] + (int32_t)(t - ptr[lo]);
+    perm[t] = k;
+    col_bm[t] = col[k];
+  }
+}
+
+// agg_idx[c] = block-major position of CSR-order segment c; row_csr[c] = its row.
+__global__ void k_rb_agg(const int32_t* __restrict__ seg_csr, const int32_t* __restrict__ seg_row,
+                         int64_t R, int32_t* __restrict__ agg_idx, int32_t* __restrict__ row_csr,
+                         float* __restrict__ ones) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < R;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = seg_csr[j];
+    agg_idx[c] = (int32_t)j;
+    row_csr[c] = seg_row[j];
+    ones[j] = 1.0f;
+  }
+}
+
+// agg_ptr[i] = first CSR-order segment of row i (row_csr is non-decreasing).
+__global__ void k_rb_agg_ptr(const int32_t* __restrict__ row_csr, int64_t R, int64_t rows,
+                             int64_t* __restrict__ agg_ptr) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= rows;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = R;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if ((int64_t)row_csr[mid] < i) lo = mid + 1; else hi = mid;
+    }
+    agg_ptr[i] = lo;
+  }
+}
+
+struct SegLen {
+  const int32_t* b;
+  const int32_t* e;
+  __device__ int64_t operator()(int64_t j) const { return (int64_t)e[j] - b[j]; }
+};
+struct OutPtr {
+  int64_t* p;
+  __device__ void operator()(int64_t j, int64_t prefix, int64_t) const { p[j] = prefix; }
+};
+
+// ---------------------------------------------------------------------------
 // dispatch helpers
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -1119,6 +1177,8 @@ int build_segments(shiro_plan plan, hipStream_t s) {
   k_seg_gather<<<grid_for(nseg), kBlock, 0, s>>>(order, nseg, sbeg, srow, nnz, sg.seg_begin,
                                                   sg.seg_end, sg.seg_row);
   SHIRO_LAUNCH_CHECK();
+  SHIRO_TRY(dev_alloc_n(&sg.seg_csr, nseg));
+  SHIRO_HIP(hipMemcpyAsync(sg.seg_csr, order, (size_t)nseg * 4, hipMemcpyDeviceToDevice, s));
   k_seg_off<<<grid_for((int64_t)P + 1), kBlock, 0, s>>>(skey, nseg, P, off);
   SHIRO_LAUNCH_CHECK();
   std::vector<int64_t> h((size_t)P + 1);
@@ -1169,17 +1229,17 @@ int launch_pack(shiro_plan plan, const void* B, int64_t ldb, int32_t N, shiro_dt
   return SHIRO_OK;
 }
 
-int launch_spmm(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* X,
-                int64_t ldx, int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy,
-                shiro_dtype out_dt, hipStream_t s) {
-  if (plan->rows == 0 || N == 0) return SHIRO_OK;
-  const WorkList* wl;
-  SHIRO_TRY(ensure_rows_work(plan, t.chunk, !stream_capturing(s), s, &wl));
-  SHIRO_TRY(ensure_carry(plan, (int64_t)wl->W * 2 * N, !stream_capturing(s)));
+namespace {
+// out[r] = sum vals[k] X[idx[k]] over a CSR-like pattern (ptr: R + 1) with
+// its work list, for the supported dtype pairs.
+int launch_pattern(shiro_plan plan, const shiro_tuning_t& t, const WorkList* wl, const int64_t* ptr,
+                   const int32_t* idx, const float* vals, int64_t R, const void* X, int64_t ldx,
+                   int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy, shiro_dtype out_dt,
+                   hipStream_t s) {
   SpmmArgs a{};
-  a.ptr = plan->row_ptr;
-  a.idx = plan->colmap;
-  a.vals = vals + plan->nz_begin;
+  a.ptr = ptr;
+  a.idx = idx;
+  a.vals = vals;
   a.X = X;
   a.ldx = ldx;
   a.out = Y;
@@ -1188,7 +1248,7 @@ int launch_spmm(shiro_plan plan, const shiro_tuning_t& t, const float* vals, con
   a.chunk_nz = wl->chunk_nz;
   a.carry = plan->carry;
   a.W = wl->W;
-  a.R = (int32_t)plan->rows;
+  a.R = (int32_t)R;
   a.N = N;
   if (in_dt == SHIRO_F32 && out_dt == SHIRO_F32) {
     const int v = vec_for<float>(N, {{X, ldx}, {Y, ldy}});
@@ -1202,7 +1262,83 @@ int launch_spmm(shiro_plan plan, const shiro_tuning_t& t, const float* vals, con
     const int v = vec_for<bf16_t>(N, {{X, ldx}, {Y, ldy}});
     return run_spmm_family<bf16_t, bf16_t>(plan, t, wl, a, v, s);
   }
-  return set_error(SHIRO_ERR_UNSUPPORTED, "spmm: dtype pair not supported (F32->F32, BF16->F32, BF16->BF16)");
+  return set_error(SHIRO_ERR_UNSUPPORTED, "dtype pair not supported (F32->F32, BF16->F32, BF16->BF16)");
+}
+}  // namespace
+
+int launch_spmm(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* X,
+                int64_t ldx, int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy,
+                shiro_dtype out_dt, hipStream_t s) {
+  if (plan->rows == 0 || N == 0) return SHIRO_OK;
+  const WorkList* wl;
+  SHIRO_TRY(ensure_rows_work(plan, t.chunk, !stream_capturing(s), s, &wl));
+  SHIRO_TRY(ensure_carry(plan, (int64_t)wl->W * 2 * N, !stream_capturing(s)));
+  return launch_pattern(plan, t, wl, plan->row_ptr, plan->colmap, vals + plan->nz_begin, plan->rows, X,
+                        ldx, N, in_dt, Y, ldy, out_dt, s);
+}
+
+int build_rowbased(shiro_plan plan, hipStream_t s) {
+  RowBased& rb = plan->rb;
+  if (rb.built) return SHIRO_OK;
+  SHIRO_TRY(build_segments(plan, s));
+  const BlockSegments& sg = plan->seg;
+  const int64_t R = sg.nseg, nnz = plan->nnz, rows = plan->rows;
+  const int32_t P = plan->P;
+  rb.R = R;
+  SHIRO_TRY(dev_alloc_n(&rb.ptr, R + 1));
+  SHIRO_TRY(dev_alloc_n(&rb.col, std::max<int64_t>(nnz, 1)));
+  SHIRO_TRY(dev_alloc_n(&rb.perm, std::max<int64_t>(nnz, 1)));
+  SHIRO_TRY(dev_alloc_n(&rb.agg_ptr, rows + 1));
+  SHIRO_TRY(dev_alloc_n(&rb.agg_idx, std::max<int64_t>(R, 1)));
+  SHIRO_TRY(dev_alloc_n(&rb.ones, std::max<int64_t>(R, 1)));
+  SHIRO_TRY(dev_alloc_n(&rb.vals, std::max<int64_t>(nnz, 1)));
+  SHIRO_TRY(dev_alloc_n(&rb.block_off, (int64_t)P + 1));
+  SHIRO_HIP(hipMemcpyAsync(rb.block_off, sg.h_off.data(), (size_t)(P + 1) * 8, hipMemcpyHostToDevice, s));
+  // the block-major copy: entry j covers nonzeros [ptr[j], ptr[j+1])
+  SHIRO_TRY(ensure_scratch(plan, scan_scratch_bytes(std::max<int64_t>(R, 1)) + (std::max<int64_t>(R, 1) * 4 + 256)));
+  char* scr = reinterpret_cast<char*>(plan->scratch);
+  int32_t* row_csr = reinterpret_cast<int32_t*>(scr);
+  void* scan_tmp = scr + (std::max<int64_t>(R, 1) * 4 + 255) / 256 * 256;
+  SHIRO_TRY(scan_generic(SegLen{sg.seg_begin, sg.seg_end}, R, OutPtr{rb.ptr}, rb.ptr + R, scan_tmp, s));
+  if (nnz > 0 && R > 0) {
+    k_rb_fill<<<grid_for(nnz), kBlock, 0, s>>>(rb.ptr, R, sg.seg_begin, plan->col, nnz, rb.perm, rb.col);
+    SHIRO_LAUNCH_CHECK();
+    k_rb_agg<<<grid_for(R), kBlock, 0, s>>>(sg.seg_csr, sg.seg_row, R, rb.agg_idx, row_csr, rb.ones);
+    SHIRO_LAUNCH_CHECK();
+  }
+  k_rb_agg_ptr<<<grid_for(rows + 1), kBlock, 0, s>>>(row_csr, R, rows, rb.agg_ptr);
+  SHIRO_LAUNCH_CHECK();
+  SHIRO_HIP(hipStreamSynchronize(s));
+  rb.built = true;
+  return SHIRO_OK;
+}
+
+int launch_partial_c(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* B,
+                     int64_t ldb, int32_t N, shiro_dtype in_dt, void* Cp, int64_t ldc,
+                     shiro_dtype out_dt, hipStream_t s) {
+  const RowBased& rb = plan->rb;
+  if (rb.R == 0 || N == 0) return SHIRO_OK;
+  const bool cap = stream_capturing(s);
+  const WorkList *wl, *wa;
+  SHIRO_TRY(ensure_rb_work(plan, t.chunk, !cap, s, &wl, &wa));
+  SHIRO_TRY(ensure_carry(plan, (int64_t)std::max(wl->W, wa->W) * 2 * N, !cap));
+  // values in block-major order (they may change from call to call)
+  k_gather_vals<<<grid_for(plan->nnz), kBlock, 0, s>>>(rb.perm, vals + plan->nz_begin, plan->nnz, rb.vals);
+  SHIRO_LAUNCH_CHECK();
+  return launch_pattern(plan, t, wl, rb.ptr, rb.col, rb.vals, rb.R, B, ldb, N, in_dt, Cp, ldc, out_dt, s);
+}
+
+int launch_aggregate_c(shiro_plan plan, const shiro_tuning_t& t, const void* Cp, int64_t ldc,
+                       int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy, shiro_dtype out_dt,
+                       hipStream_t s) {
+  const RowBased& rb = plan->rb;
+  if (plan->rows == 0 || N == 0) return SHIRO_OK;
+  const bool cap = stream_capturing(s);
+  const WorkList *wl, *wa;
+  SHIRO_TRY(ensure_rb_work(plan, t.chunk, !cap, s, &wl, &wa));
+  SHIRO_TRY(ensure_carry(plan, (int64_t)std::max(wl->W, wa->W) * 2 * N, !cap));
+  return launch_pattern(plan, t, wa, rb.agg_ptr, rb.agg_idx, rb.ones, plan->rows, Cp, ldc, N, in_dt, Y, ldy,
+                        out_dt, s);
 }
 
 int launch_spmm_t(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* dY,

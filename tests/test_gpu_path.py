@@ -381,6 +381,75 @@ def test_autotune_then_correct(shiro, monkeypatch, tmp_path):
     assert len(lines) == 3 and all(ln.split()[0].endswith(("|k=0", "|k=1", "|k=2")) for ln in lines)
 
 
+# ----------------------------------------------------------------------------
+# row-based scheme: Rows(A^(p,q)), partial C rows, their sum into the panel
+# ----------------------------------------------------------------------------
+def test_c_rows_bit_exact(shiro, run):
+    R, per = shiro.select_c_rows(run.plan)
+    rs, off = oracle.select_c_rows(run.Ac)
+    assert R == len(rs) and per == list(np.diff(off))
+    grs, goff = shiro.c_row_selection(run.plan, R)
+    assert np.array_equal(grs.cpu().numpy(), rs)
+    assert np.array_equal(goff.cpu().numpy(), off)
+
+
+def test_partial_and_aggregate_f32(shiro, run):
+    R, _ = shiro.select_c_rows(run.plan)
+    rs, off = oracle.select_c_rows(run.Ac)
+    B = run.B.to(run.dev)
+    Cp = shiro.partial_c(run.plan, run.Ad.vals, B, R)
+    Bn = run.B.numpy()
+    ref = oracle.partial_c(run.Ac, Bn, rs, off)
+    den = oracle.partial_c(run.Ac, Bn, rs, off, abs_mode=True)
+    assert oracle.rel_err(Cp.cpu().numpy(), ref, den) <= TOL_F32
+    Y = shiro.aggregate_c(run.plan, Cp)
+    Yref, Yden = _fwd_ref(run, Bn)
+    assert oracle.rel_err(Y.cpu().numpy(), Yref, Yden) <= TOL_F32
+    # the sum on its own, on seeded partial rows (integers: exact in any order)
+    rng = np.random.default_rng(3)
+    Cx = rng.integers(-4, 5, size=(R, run.N)).astype(np.float32)
+    Yx = shiro.aggregate_c(run.plan, torch.from_numpy(Cx).to(run.dev))
+    assert np.array_equal(Yx.cpu().numpy(), oracle.aggregate_c(run.Ac, Cx, rs, off))
+    # reproducible
+    assert torch.equal(shiro.partial_c(run.plan, run.Ad.vals, B, R), Cp)
+
+
+def test_partial_and_aggregate_bf16(shiro, run):
+    R, _ = shiro.select_c_rows(run.plan)
+    rs, off = oracle.select_c_rows(run.Ac)
+    Bh = run.B.to(torch.bfloat16).to(run.dev)
+    Bn = run.B.numpy()
+    Yref, Yden = _fwd_ref(run, Bn)
+    for mid in (torch.bfloat16, torch.float32):
+        Cp = shiro.partial_c(run.plan, run.Ad.vals, Bh, R, out_dtype=mid)
+        ref = oracle.partial_c(run.Ac, Bn, rs, off)
+        den = oracle.partial_c(run.Ac, Bn, rs, off, abs_mode=True)
+        assert oracle.rel_err(bf16_to_f32(Cp), ref, den) <= TOL_BF16
+        for out_dtype in ((torch.bfloat16, torch.float32) if mid == torch.bfloat16 else (torch.float32,)):
+            Y = shiro.aggregate_c(run.plan, Cp, out_dtype=out_dtype)
+            assert oracle.rel_err(bf16_to_f32(Y), Yref, Yden) <= TOL_BF16
+
+
+def test_row_based_graph_replays(shiro, run):
+    R, _ = shiro.select_c_rows(run.plan)
+    shiro.prepare(run.plan, run.N, torch.float32, ops=("row_based",))
+    B = run.B.to(run.dev)
+    Cp = torch.empty(R, run.N, device=run.dev)
+    Y = torch.empty(run.Ac.M, run.N, device=run.dev)
+    ref = shiro.aggregate_c(run.plan, shiro.partial_c(run.plan, run.Ad.vals, B, R))
+    cs = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with run.plan.capture(cs) as gid:
+        shiro.partial_c(run.plan, run.Ad.vals, B, R, out=Cp, stream=cs)
+        shiro.aggregate_c(run.plan, Cp, out=Y, stream=cs)
+    for _ in range(3):
+        Y.fill_(float("nan"))
+        torch.cuda.synchronize()
+        run.plan.replay(gid[0], stream=cs)
+        cs.synchronize()
+        assert torch.equal(Y, ref)
+
+
 def test_torch_allocator(shiro):
     """Plan memory from torch's caching allocator: accounted by torch while the
     plan lives, returned when it is destroyed, results unchanged."""
