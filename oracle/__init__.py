@@ -278,3 +278,81 @@ def aggregate_c(A: Csr, Cp: np.ndarray, row_sel, rblock_off) -> np.ndarray:
     lib().oracle_aggregate_c(A.M, A.P, _ptr(rs), _ptr(_c(rblock_off, np.int64)), _ptr(cd), _ptr(cf), N, N,
                              _ptr(Y), N)
     return Y[:A.M]
+
+
+# ----------------------------------------------------------------------------
+# joint row-column strategy (Sec. 5.2 problem; Sec. 5.3 minimum weighted
+# vertex cover of the bipartite graph, solved as a minimum s-t cut)
+# ----------------------------------------------------------------------------
+def mvc_bipartite(n_left: int, n_right: int, edges, w_left=None, w_right=None):
+    """Minimum weighted vertex cover of a bipartite graph (left = rows of C,
+    right = rows of B; edges = nonzeros) by the flow network of Sec. 5.3:
+    s -> left i with capacity w_left[i], left -> right with capacity larger
+    than any cut, right j -> t with capacity w_right[j]; the cover is the
+    left vertices cut off from s plus the right vertices still reachable from
+    s in the residual graph.  Max flow by scipy (a library step).
+    Returns (weight, cover_left bool[n_left], cover_right bool[n_right])."""
+    import scipy.sparse as sps
+    from scipy.sparse.csgraph import maximum_flow
+
+    edges = np.asarray(edges, np.int64).reshape(-1, 2)
+    wl = np.ones(n_left, np.int64) if w_left is None else np.asarray(w_left, np.int64)
+    wr = np.ones(n_right, np.int64) if w_right is None else np.asarray(w_right, np.int64)
+    if len(edges) == 0:
+        return 0, np.zeros(n_left, bool), np.zeros(n_right, bool)
+    big = int(wl.sum() + wr.sum() + 1)
+    s, t = n_left + n_right, n_left + n_right + 1
+    V = n_left + n_right + 2
+    src = np.concatenate([np.full(n_left, s), edges[:, 0], n_left + np.arange(n_right)])
+    dst = np.concatenate([np.arange(n_left), n_left + edges[:, 1], np.full(n_right, t)])
+    cap = np.concatenate([wl, np.full(len(edges), big), wr])
+    G = sps.csr_array((cap.astype(np.int64), (src, dst)), shape=(V, V))
+    G.sum_duplicates()
+    res = maximum_flow(G, s, t)
+    F = res.flow.tocsr()
+    # residual graph: forward capacity left, and reverse capacity = flow
+    Gc = G.tocoo()
+    fwd = sps.csr_array((Gc.data - F[Gc.row, Gc.col], (Gc.row, Gc.col)), shape=(V, V))
+    Fc = F.tocoo()
+    pos = Fc.data > 0
+    back = sps.csr_array((Fc.data[pos], (Fc.col[pos], Fc.row[pos])), shape=(V, V))
+    Rg = (fwd + back).tocsr()
+    seen = np.zeros(V, bool)
+    seen[s] = True
+    stack = [s]
+    while stack:
+        u = stack.pop()
+        for k in range(Rg.indptr[u], Rg.indptr[u + 1]):
+            v = Rg.indices[k]
+            if Rg.data[k] > 0 and not seen[v]:
+                seen[v] = True
+                stack.append(v)
+    cover_left = ~seen[:n_left]
+    cover_right = seen[n_left:n_left + n_right]
+    weight = int(wl[cover_left].sum() + wr[cover_right].sum())
+    assert weight == int(res.flow_value)  # max-flow min-cut
+    return weight, cover_left, cover_right
+
+
+def joint_cover(A: Csr, w_row=None, w_col=None):
+    """Per column block q: (mu_q, Rows_q, Cols_q, rows in the cover, cols in
+    the cover) for the off-diagonal blocks (q != p); None for the diagonal
+    block, whose B rows are local.  w_row: cost per panel row (panel-local
+    index), w_col: cost per global column; None means unit costs."""
+    out = []
+    nz0 = A.nz_begin
+    rows_of = np.repeat(np.arange(A.M), np.diff(A.row_ptr[A.row_begin:A.row_end + 1]))
+    cols = A.col[nz0:nz0 + A.nnz_panel].astype(np.int64)
+    for q in range(A.P):
+        if q == A.p:
+            out.append(None)
+            continue
+        m = (cols // A.K) == q
+        r, c = rows_of[m], cols[m]
+        ur, ri = np.unique(r, return_inverse=True)
+        uc, ci = np.unique(c, return_inverse=True)
+        wl = None if w_row is None else np.asarray(w_row)[ur]
+        wr = None if w_col is None else np.asarray(w_col)[uc]
+        mu, cl, cr = mvc_bipartite(len(ur), len(uc), np.stack([ri, ci], 1), wl, wr)
+        out.append((mu, ur, uc, ur[cl], uc[cr]))
+    return out

@@ -460,3 +460,79 @@ def test_aggregate_is_indexed_add():
     ref = np.zeros((A.M, 3))
     np.add.at(ref, rs, Cp.astype(np.float64))
     assert np.array_equal(Y, ref)
+
+
+# ----------------------------------------------------------------------------
+# joint strategy: minimum (weighted) vertex cover per block (Sec. 5.2-5.4)
+# ----------------------------------------------------------------------------
+def brute_mvc(n_left, n_right, edges, wl, wr):
+    best = None
+    n = n_left + n_right
+    w = np.concatenate([wl, wr])
+    for mask in range(1 << n):
+        sel = [(mask >> v) & 1 for v in range(n)]
+        if all(sel[i] or sel[n_left + j] for i, j in edges):
+            cost = sum(w[v] for v in range(n) if sel[v])
+            best = cost if best is None else min(best, cost)
+    return best
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_mvc_matches_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    nl, nr = int(rng.integers(1, 7)), int(rng.integers(1, 7))
+    mask = rng.random((nl, nr)) < 0.45
+    edges = np.argwhere(mask)
+    weighted = seed % 2 == 1
+    wl = rng.integers(1, 9, nl) if weighted else np.ones(nl, np.int64)
+    wr = rng.integers(1, 9, nr) if weighted else np.ones(nr, np.int64)
+    mu, cl, cr = oracle.mvc_bipartite(nl, nr, edges, wl, wr)
+    assert mu == brute_mvc(nl, nr, edges, wl, wr)
+    assert all(cl[i] or cr[j] for i, j in edges)  # a cover
+    assert mu == int(wl[cl].sum() + wr[cr].sum())
+
+
+def test_mvc_unit_costs_is_max_matching():
+    """Koenig: with unit costs the minimum cover has the size of a maximum matching."""
+    from scipy.sparse import csr_array
+    from scipy.sparse.csgraph import maximum_bipartite_matching
+
+    rng = np.random.default_rng(4)
+    for _ in range(6):
+        nl, nr = 60, 45
+        mask = rng.random((nl, nr)) < 0.05
+        edges = np.argwhere(mask)
+        mu, cl, cr = oracle.mvc_bipartite(nl, nr, edges)
+        match = maximum_bipartite_matching(csr_array(mask.astype(np.int8)), perm_type="column")
+        assert mu == int((match >= 0).sum())
+        assert all(cl[i] or cr[j] for i, j in edges)
+
+
+def test_joint_cover_fig1_worked_example():
+    g = load_golden("fig1_block01.txt")
+    n, P, p = g["n"][0][0], g["P"][0][0], g["p"][0][0]
+    mask = np.zeros((n, n))
+    for r, c, v in g["nz"]:
+        mask[r, c] = v
+    Ac = oracle.Csr.from_synth(synth.from_dense_pattern(mask, P=P, p=p))
+    res = oracle.joint_cover(Ac)
+    (q, mu), = g["expect_joint_cover_block"]
+    assert res[p] is None
+    assert res[q][0] == mu
+    (_, *rows), = g["expect_joint_rows"]
+    (_, *cols), = g["expect_joint_cols"]
+    assert list(res[q][3]) == rows and list(res[q][4]) == cols
+
+
+def test_joint_cover_bounds_rmat():
+    """mu <= min(|Rows|, |Cols|) per block (the dominance of Sec. 5.4)."""
+    A = oracle.Csr.from_synth(synth.small_rmat(10, 8, P=8, p=2))
+    uc, off, _ = oracle.select(A)
+    rs, roff = oracle.select_c_rows(A)
+    for q, r in enumerate(oracle.joint_cover(A)):
+        if r is None:
+            continue
+        mu, rows, cols, crow, ccol = r
+        assert len(cols) == off[q + 1] - off[q] and len(rows) == roff[q + 1] - roff[q]
+        assert mu <= min(len(rows), len(cols))
+        assert mu == len(crow) + len(ccol)
