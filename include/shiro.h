@@ -106,6 +106,9 @@ enum {
 #define SHIRO_MODE_BATCHED 0u   /* all column blocks in one persistent launch, row-merged */
 #define SHIRO_MODE_PER_BLOCK 1u /* one launch per column block, summed in block order     */
 
+/* shiro_aggregate_c flags */
+#define SHIRO_AGG_ACCUMULATE 1u /* add the sums into Y instead of overwriting Y */
+
 /* shiro_spmm_backward flags */
 #define SHIRO_DB_OVERWRITE 1u /* dB rows at unique_cols are overwritten instead of added to */
 
@@ -162,6 +165,22 @@ SHIRO_API int shiro_partition(int64_t n_rows, int64_t n_cols, int64_t nnz,
                               const int64_t* d_row_ptr, const int32_t* d_col, int32_t P,
                               int32_t p, uint32_t flags, shiro_stream_t stream,
                               shiro_plan* out_plan);
+
+/* A plan over part of the panel's nonzeros: those k of panel p (counted
+ * from the panel's first nonzero) with d_keep[k] == keep_value, in CSR
+ * order, with the global shape, P and p of shiro_partition.  The joint
+ * strategy (Sec. 5.1 step 2) splits each block into a row-based and a
+ * column-based part; each part is a subset plan.  Compute calls take the
+ * caller's whole value array (indexed like d_col, as for a full plan) and
+ * read it through the subset's map; dvals of spmm_backward are written for
+ * the subset's nonzeros only.  d_keep: device, one byte per panel nonzero.
+ * The per-block spmm mode is not available on subset plans (UNSUPPORTED).
+ * Other arguments and errors as shiro_partition. */
+SHIRO_API int shiro_partition_subset(int64_t n_rows, int64_t n_cols, int64_t nnz,
+                                     const int64_t* d_row_ptr, const int32_t* d_col,
+                                     const uint8_t* d_keep, uint8_t keep_value, int32_t P,
+                                     int32_t p, uint32_t flags, shiro_stream_t stream,
+                                     shiro_plan* out_plan);
 
 SHIRO_API int shiro_plan_info(shiro_plan plan, shiro_plan_info_t* h_info);
 
@@ -279,11 +298,47 @@ SHIRO_API int shiro_partial_c(shiro_plan plan, const float* d_vals, const void* 
 
 /* The receiver's sum: d_Y (rows x N, ldy, out_dt) overwritten with the sum
  * of each panel row's partial rows from d_Cp (R x N, ldc, in_dt), blocks in
- * ascending order; rows with no entry get 0.  Same pairs and errors as
- * shiro_partial_c. */
+ * ascending order; rows with no entry get 0.  With flags &
+ * SHIRO_AGG_ACCUMULATE the sums are added to d_Y instead (rows with no
+ * entry unchanged): the joint strategy adds the row-based part to the
+ * column-based product.  Same pairs and errors as shiro_partial_c; unknown
+ * flag bits: INVALID_ARG. */
 SHIRO_API int shiro_aggregate_c(shiro_plan plan, const void* d_Cp, int64_t ldc, int32_t N,
                                 shiro_dtype in_dt, void* d_Y, int64_t ldy, shiro_dtype out_dt,
-                                shiro_stream_t stream);
+                                uint32_t flags, shiro_stream_t stream);
+
+/* ---- Joint row-column strategy (Sec. 5.2 problem; Sec. 5.3 minimum
+ * weighted vertex cover by minimum s-t cut; Sec. 5.4 volumes) ------------
+ * Host routines (the paper plans offline on the CPU, once per pattern).
+ *
+ * Minimum weighted vertex cover of a bipartite graph: left vertices are
+ * rows of C (row-based sends), right vertices rows of B (column-based
+ * fetches), edge e joins h_left[e] and h_right[e] (one per nonzero).
+ * Costs h_w_left[n_left], h_w_right[n_right] (>= 0; NULL = all 1).  Writes
+ * h_cover_left/right (1 = in the cover) and the cover's cost *h_weight.
+ * Max flow by Dinic's algorithm.  Several optimal covers may exist; the one
+ * returned is the source side of the minimum cut.  INVALID_ARG on bad sizes,
+ * out-of-range endpoints or negative costs. */
+SHIRO_API int shiro_mvc_bipartite(int64_t n_left, int64_t n_right, int64_t n_edges,
+                                  const int32_t* h_left, const int32_t* h_right,
+                                  const int64_t* h_w_left, const int64_t* h_w_right,
+                                  uint8_t* h_cover_left, uint8_t* h_cover_right,
+                                  int64_t* h_weight);
+
+/* Joint plan of the panel: the cover above for every off-diagonal block
+ * A^(p,q) (the diagonal block uses local B rows and is not planned), blocks
+ * solved in parallel on n_threads host threads (0 = up to 16).
+ * h_w_row: cost per panel row (rows entries, panel-local index), h_w_col:
+ * cost per global column (n_cols entries); NULL = unit costs.
+ * h_assign (nnz bytes, nullable): 1 for a nonzero computed row-based (its
+ * row is in its block's cover), 0 for column-based (and for the diagonal
+ * block).  h_stats (5*P int64, nullable): per block q, cover cost mu_q,
+ * |Rows(A^(p,q))|, |Cols(A^(p,q))|, rows in the cover, columns in the cover
+ * (mu and the cover counts are 0 for the diagonal block).  Copies the
+ * pattern to the host and synchronises the stream. */
+SHIRO_API int shiro_joint_plan(shiro_plan plan, const int64_t* h_w_row, const int64_t* h_w_col,
+                               uint8_t* h_assign, int64_t* h_stats, int32_t n_threads,
+                               shiro_stream_t stream);
 
 /* Build everything the per-call steps need for (N, dtype, ops) - work lists,
  * transposed pattern, carry buffers - so later calls neither allocate nor

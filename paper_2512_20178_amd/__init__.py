@@ -32,6 +32,10 @@ __all__ = [
     "c_row_selection",
     "partial_c",
     "aggregate_c",
+    "partition_subset",
+    "JointSpMM",
+    "mvc_bipartite",
+    "joint_plan",
     "prepare",
     "autotune",
     "get_tuning",
@@ -184,6 +188,23 @@ def partition(row_ptr: torch.Tensor, col: torch.Tensor, n_rows: int, n_cols: int
     return Plan(h.value, row_ptr.device)
 
 
+def partition_subset(row_ptr: torch.Tensor, col: torch.Tensor, n_rows: int, n_cols: int, P: int, p: int,
+                     keep: torch.Tensor, keep_value: int, check: bool = False, stream=None) -> Plan:
+    """Plan over the panel's nonzeros k with keep[k] == keep_value (keep: uint8
+    on the device, one entry per nonzero of panel p)."""
+    _dev(row_ptr)
+    _dev(keep)
+    if row_ptr.dtype != torch.int64 or col.dtype != torch.int32 or keep.dtype != torch.uint8:
+        raise TypeError("row_ptr int64, col int32, keep uint8")
+    h = ctypes.c_void_p()
+    nnz = col.numel()
+    _lib.check(_L().shiro_partition_subset(int(n_rows), int(n_cols), int(nnz), _ptr(row_ptr.contiguous()),
+                                           _ptr(col.contiguous()) if nnz else None, _ptr(keep.contiguous()),
+                                           int(keep_value), int(P), int(p), _lib.CHECK_CSR if check else 0,
+                                           ctypes.c_void_p(_stream(stream)), ctypes.byref(h)))
+    return Plan(h.value, row_ptr.device)
+
+
 def select_rows(plan: Plan, stream=None) -> Tuple[int, list]:
     """Run the selection; returns (U, [|Cols_q| for q in range(P)])."""
     P = plan.info()["P"]
@@ -302,15 +323,94 @@ def partial_c(plan: Plan, vals: torch.Tensor, B: torch.Tensor, R: int, out: Opti
 
 
 def aggregate_c(plan: Plan, Cp: torch.Tensor, out: Optional[torch.Tensor] = None, out_dtype=None,
-                stream=None) -> torch.Tensor:
-    """Y[i] = sum over blocks (ascending) of row i's partial rows (rows x N)."""
+                accumulate: bool = False, stream=None) -> torch.Tensor:
+    """Y[i] = sum over blocks (ascending) of row i's partial rows (rows x N);
+    with accumulate the sums are added to `out`."""
     _dev(Cp)
     N = Cp.shape[1]
     if out is None:
+        if accumulate:
+            raise ValueError("accumulate needs out")
         out = torch.empty(plan.rows, N, dtype=out_dtype or Cp.dtype, device=Cp.device)
     _lib.check(_L().shiro_aggregate_c(plan.handle, _ptr(Cp), _ld(Cp), N, _dt(Cp.dtype), _ptr(out), _ld(out),
-                                      _dt(out.dtype), ctypes.c_void_p(_stream(stream))))
+                                      _dt(out.dtype), _lib.AGG_ACCUMULATE if accumulate else 0,
+                                      ctypes.c_void_p(_stream(stream))))
     return out
+
+
+class JointSpMM:
+    """The joint row-column strategy on panel p (Sec. 5.1 steps 1-5): plan the
+    per-block covers on the host, split the panel into a column-based and a
+    row-based subset plan, then Y = A_col B (select / pack / spmm) plus the
+    row-based partial rows of A_row B summed into Y."""
+
+    def __init__(self, row_ptr, col, n_rows, n_cols, P, p, w_row=None, w_col=None, n_threads=0):
+        base = partition(row_ptr, col, n_rows, n_cols, P, p)
+        self.assign, self.stats = joint_plan(base, w_row, w_col, n_threads)
+        base.close()
+        keep = self.assign.to(row_ptr.device)
+        if keep.numel() == 0:
+            keep = torch.zeros(1, dtype=torch.uint8, device=row_ptr.device)
+        self.col_plan = partition_subset(row_ptr, col, n_rows, n_cols, P, p, keep, 0)
+        self.row_plan = partition_subset(row_ptr, col, n_rows, n_cols, P, p, keep, 1)
+        self.U, self.Uq = select_rows(self.col_plan)
+        self.R, self.Rq = select_c_rows(self.row_plan)
+
+    def prepare(self, N: int, dtype=torch.float32):
+        prepare(self.col_plan, N, dtype, ops=("spmm",))
+        prepare(self.row_plan, N, dtype, ops=("row_based",))
+
+    def forward(self, vals: torch.Tensor, B: torch.Tensor, out: Optional[torch.Tensor] = None,
+                Bp: Optional[torch.Tensor] = None, Cp: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        Bp = pack_B(self.col_plan, B, out=Bp, stream=stream)
+        Y = spmm(self.col_plan, vals, Bp, out=out, stream=stream)
+        Cp = partial_c(self.row_plan, vals, B, self.R, out=Cp, stream=stream)
+        return aggregate_c(self.row_plan, Cp, out=Y, accumulate=True, stream=stream)
+
+
+# ---------------------------------------------------------------------------
+# joint row-column strategy (host planner)
+# ---------------------------------------------------------------------------
+def _host_i64(a, n):
+    if a is None:
+        return None, None
+    t = torch.as_tensor(a, dtype=torch.int64).contiguous().cpu()
+    if t.numel() != n:
+        raise ValueError(f"expected {n} costs, got {t.numel()}")
+    return t, ctypes.c_void_p(t.data_ptr())
+
+
+def mvc_bipartite(n_left: int, n_right: int, left, right, w_left=None, w_right=None):
+    """Minimum weighted vertex cover of a bipartite graph (host):
+    returns (cost, cover_left bool tensor, cover_right bool tensor)."""
+    le = torch.as_tensor(left, dtype=torch.int32).contiguous().cpu()
+    ri = torch.as_tensor(right, dtype=torch.int32).contiguous().cpu()
+    if le.numel() != ri.numel():
+        raise ValueError("left and right must have one entry per edge")
+    wl, pwl = _host_i64(w_left, n_left)
+    wr, pwr = _host_i64(w_right, n_right)
+    cl = torch.zeros(max(n_left, 1), dtype=torch.uint8)
+    cr = torch.zeros(max(n_right, 1), dtype=torch.uint8)
+    w = ctypes.c_int64()
+    _lib.check(_L().shiro_mvc_bipartite(int(n_left), int(n_right), le.numel(), ctypes.c_void_p(le.data_ptr()),
+                                        ctypes.c_void_p(ri.data_ptr()), pwl, pwr, ctypes.c_void_p(cl.data_ptr()),
+                                        ctypes.c_void_p(cr.data_ptr()), ctypes.byref(w)))
+    return w.value, cl[:n_left].bool(), cr[:n_right].bool()
+
+
+def joint_plan(plan: Plan, w_row=None, w_col=None, n_threads: int = 0, stream=None):
+    """Per-block minimum covers of the panel (host).  Returns (assign uint8
+    tensor over the panel's nonzeros: 1 = row-based, stats int64 (P, 5): cover
+    cost, |Rows_q|, |Cols_q|, rows in the cover, columns in the cover)."""
+    inf = plan.info()
+    wr_, pwr = _host_i64(w_row, inf["rows"])
+    wc_, pwc = _host_i64(w_col, inf["n_cols"])
+    assign = torch.zeros(max(inf["nnz"], 1), dtype=torch.uint8)
+    stats = torch.zeros(inf["P"], 5, dtype=torch.int64)
+    _lib.check(_L().shiro_joint_plan(plan.handle, pwr, pwc, ctypes.c_void_p(assign.data_ptr()),
+                                     ctypes.c_void_p(stats.data_ptr()), int(n_threads),
+                                     ctypes.c_void_p(_stream(stream))))
+    return assign[:inf["nnz"]], stats
 
 
 _OPS = {"spmm": _lib.OP_SPMM, "backward": _lib.OP_BACKWARD, "per_block": _lib.OP_PER_BLOCK,

@@ -33,6 +33,7 @@ MODE_BATCHED = 0
 MODE_PER_BLOCK = 1
 
 DB_OVERWRITE = 1
+AGG_ACCUMULATE = 1
 OP_SPMM = 1
 OP_BACKWARD = 2
 OP_PER_BLOCK = 4
@@ -49,6 +50,7 @@ EXPORTS = [
     "shiro_version",
     "shiro_last_error",
     "shiro_partition",
+    "shiro_partition_subset",
     "shiro_plan_info",
     "shiro_block_nnz",
     "shiro_select_rows",
@@ -62,6 +64,8 @@ EXPORTS = [
     "shiro_copy_c_row_selection",
     "shiro_partial_c",
     "shiro_aggregate_c",
+    "shiro_mvc_bipartite",
+    "shiro_joint_plan",
     "shiro_prepare",
     "shiro_autotune",
     "shiro_get_tuning",
@@ -149,7 +153,11 @@ def load(path: str = LIB_PATH):
         L.shiro_select_c_rows.argtypes = [_p, _p, ctypes.POINTER(_i64), _p]
         L.shiro_copy_c_row_selection.argtypes = [_p, _p, _p, _p]
         L.shiro_partial_c.argtypes = [_p, _p, _p, _i64, _i32, ctypes.c_int, _p, _i64, ctypes.c_int, _p]
-        L.shiro_aggregate_c.argtypes = [_p, _p, _i64, _i32, ctypes.c_int, _p, _i64, ctypes.c_int, _p]
+        L.shiro_aggregate_c.argtypes = [_p, _p, _i64, _i32, ctypes.c_int, _p, _i64, ctypes.c_int, _u32, _p]
+        L.shiro_partition_subset.argtypes = [_i64, _i64, _i64, _p, _p, _p, ctypes.c_uint8, _i32, _i32, _u32, _p,
+                                             ctypes.POINTER(_p)]
+        L.shiro_mvc_bipartite.argtypes = [_i64, _i64, _i64, _p, _p, _p, _p, _p, _p, ctypes.POINTER(_i64)]
+        L.shiro_joint_plan.argtypes = [_p, _p, _p, _p, _p, _i32, _p]
         L.shiro_prepare.argtypes = [_p, _i32, ctypes.c_int, _u32, _p]
         L.shiro_autotune.argtypes = [_p, _i32, ctypes.c_int, _u32, _p]
         L.shiro_get_tuning.argtypes = [_p, _i32, _i32, ctypes.c_int, ctypes.POINTER(Tuning)]

@@ -247,6 +247,8 @@ static void plan_free(shiro_plan plan) {
     if (g) (void)hipGraphExecDestroy(g);
   dev_free(plan->row_ptr);
   dev_free(plan->col);
+  dev_free(plan->vmap);
+  dev_free(plan->svals);
   dev_free(plan->flags);
   dev_free(plan->wtab);
   dev_free(plan->unique_cols);
@@ -273,6 +275,7 @@ static void plan_free(shiro_plan plan) {
   dev_free(plan->rb.agg_ptr);
   dev_free(plan->rb.agg_idx);
   dev_free(plan->rb.ones);
+  dev_free(plan->rb.iota);
   dev_free(plan->rb.vals);
   dev_free(plan->rb.block_off);
   dev_free(plan->carry);
@@ -447,9 +450,9 @@ SHIRO_API int shiro_version(void) { return 10000; }
 
 SHIRO_API const char* shiro_last_error(void) { return g_last_error.c_str(); }
 
-SHIRO_API int shiro_partition(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t* d_row_ptr,
-                              const int32_t* d_col, int32_t P, int32_t p, uint32_t flags,
-                              shiro_stream_t stream, shiro_plan* out_plan) {
+static int partition_impl(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t* d_row_ptr,
+                          const int32_t* d_col, const uint8_t* d_keep, uint8_t keep_val, int32_t P, int32_t p,
+                          uint32_t flags, shiro_stream_t stream, shiro_plan* out_plan) {
   if (!out_plan) return set_error(SHIRO_ERR_INVALID_ARG, "partition: out_plan is NULL");
   *out_plan = nullptr;
   if (n_rows < 1 || n_cols < 1 || n_rows >= (1ll << 31) || n_cols >= (1ll << 31))
@@ -495,23 +498,53 @@ SHIRO_API int shiro_partition(int64_t n_rows, int64_t n_cols, int64_t nnz, const
     return fail(set_error(SHIRO_ERR_UNSUPPORTED, "partition: panel has 2^31 or more nonzeros"));
   plan->nz_begin = nz0;
   plan->nnz = nz1 - nz0;
+  plan->src_nnz = plan->nnz;
   plan->n_words = ceil_div(n_cols, 32);
 
   int rc;
-  if ((rc = dev_alloc_n(&plan->row_ptr, plan->rows + 1)) ||
-      (rc = dev_alloc_n(&plan->col, std::max<int64_t>(plan->nnz, 1))) ||
+  if (d_keep) {
+    // keep the panel nonzeros k with d_keep[k] == keep_val, in CSR order
+    const int64_t n = plan->nnz;
+    if ((rc = ensure_scratch(plan, (n + 1) * 8 + 256 + scan_scratch_bytes(std::max<int64_t>(n, 1))))) return fail(rc);
+    int64_t* pos = reinterpret_cast<int64_t*>(plan->scratch);
+    void* scan_tmp = reinterpret_cast<char*>(plan->scratch) + ((n + 1) * 8 + 255) / 256 * 256;
+    int32_t* col_tmp = nullptr;
+    if ((rc = dev_alloc_n(&col_tmp, std::max<int64_t>(n, 1))) ||
+        (rc = dev_alloc_n(&plan->vmap, std::max<int64_t>(n, 1))) ||
+        (rc = dev_alloc_n(&plan->row_ptr, plan->rows + 1))) {
+      dev_free(col_tmp);
+      return fail(rc);
+    }
+    rc = launch_subset(d_row_ptr + plan->row_begin, plan->rows, nz0, n, d_col + nz0, d_keep, keep_val, pos,
+                       col_tmp, plan->vmap, plan->row_ptr, scan_tmp, s);
+    if (rc == SHIRO_OK &&
+        (hipMemcpyAsync(plan->h_pinned, pos + n, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+         hipStreamSynchronize(s) != hipSuccess))
+      rc = set_error(SHIRO_ERR_HIP, "partition_subset: counting the kept nonzeros failed");
+    if (rc != SHIRO_OK) {
+      dev_free(col_tmp);
+      return fail(rc);
+    }
+    plan->nnz = plan->h_pinned[0];
+    plan->col = col_tmp;  // first n entries hold the kept columns
+    if ((rc = dev_alloc_n(&plan->svals, std::max<int64_t>(plan->nnz, 1)))) return fail(rc);
+  }
+  if ((!d_keep && ((rc = dev_alloc_n(&plan->row_ptr, plan->rows + 1)) ||
+                   (rc = dev_alloc_n(&plan->col, std::max<int64_t>(plan->nnz, 1))))) ||
       (rc = dev_alloc_n(&plan->flags, plan->n_words * 32)) ||
       (rc = dev_alloc_n(&plan->wtab, 2 * plan->n_words)) ||
       (rc = dev_alloc_n(&plan->unique_cols, std::max<int64_t>(std::min(plan->nnz, n_cols), 1))) ||
       (rc = dev_alloc_n(&plan->block_off, (int64_t)P + 1)) ||
       (rc = dev_alloc_n(&plan->colmap, std::max<int64_t>(plan->nnz, 1))))
     return fail(rc);
-  if ((rc = launch_rebase_row_ptr(d_row_ptr + plan->row_begin, plan->rows, plan->row_ptr, s))) return fail(rc);
+  if (!d_keep) {
+    if ((rc = launch_rebase_row_ptr(d_row_ptr + plan->row_begin, plan->rows, plan->row_ptr, s))) return fail(rc);
+    if (plan->nnz > 0 &&
+        hipMemcpyAsync(plan->col, d_col + nz0, (size_t)plan->nnz * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return fail(set_error(SHIRO_ERR_HIP, "partition: copying the panel's columns failed"));
+  }
   // the selection expects all-zero flags (each selection clears what it set)
   if ((rc = launch_zero_bytes(plan->flags, plan->n_words * 32, s))) return fail(rc);
-  if (plan->nnz > 0 &&
-      hipMemcpyAsync(plan->col, d_col + nz0, (size_t)plan->nnz * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
-    return fail(set_error(SHIRO_ERR_HIP, "partition: copying the panel's columns failed"));
 
   if ((flags & SHIRO_CHECK_CSR) || env_check()) {
     if ((rc = ensure_scratch(plan, 256))) return fail(rc);
@@ -534,6 +567,20 @@ SHIRO_API int shiro_partition(int64_t n_rows, int64_t n_cols, int64_t nnz, const
   if (hipStreamSynchronize(s) != hipSuccess) return fail(set_error(SHIRO_ERR_HIP, "partition: stream failed"));
   *out_plan = plan;
   return SHIRO_OK;
+}
+
+SHIRO_API int shiro_partition(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t* d_row_ptr,
+                              const int32_t* d_col, int32_t P, int32_t p, uint32_t flags,
+                              shiro_stream_t stream, shiro_plan* out_plan) {
+  return partition_impl(n_rows, n_cols, nnz, d_row_ptr, d_col, nullptr, 0, P, p, flags, stream, out_plan);
+}
+
+SHIRO_API int shiro_partition_subset(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t* d_row_ptr,
+                                     const int32_t* d_col, const uint8_t* d_keep, uint8_t keep_value, int32_t P,
+                                     int32_t p, uint32_t flags, shiro_stream_t stream, shiro_plan* out_plan) {
+  if (!d_keep) return set_error(SHIRO_ERR_INVALID_ARG, "partition_subset: d_keep is NULL");
+  return partition_impl(n_rows, n_cols, nnz, d_row_ptr, d_col, d_keep, keep_value, P, p, flags, stream,
+                        out_plan);
 }
 
 SHIRO_API int shiro_plan_info(shiro_plan plan, shiro_plan_info_t* h_info) {
@@ -711,8 +758,10 @@ SHIRO_API int shiro_partial_c(shiro_plan plan, const float* d_vals, const void* 
 }
 
 SHIRO_API int shiro_aggregate_c(shiro_plan plan, const void* d_Cp, int64_t ldc, int32_t N, shiro_dtype in_dt,
-                                void* d_Y, int64_t ldy, shiro_dtype out_dt, shiro_stream_t stream) {
+                                void* d_Y, int64_t ldy, shiro_dtype out_dt, uint32_t flags,
+                                shiro_stream_t stream) {
   if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "aggregate_c: plan is NULL");
+  if (flags & ~SHIRO_AGG_ACCUMULATE) return set_error(SHIRO_ERR_INVALID_ARG, "aggregate_c: unknown flags");
   if (!plan->rb.built) return set_error(SHIRO_ERR_NOT_READY, "aggregate_c: call shiro_select_c_rows first");
   if (!valid_pair(in_dt, out_dt))
     return set_error(SHIRO_ERR_UNSUPPORTED, "aggregate_c: dtype pair not supported (F32->F32, BF16->F32, BF16->BF16)");
@@ -721,7 +770,38 @@ SHIRO_API int shiro_aggregate_c(shiro_plan plan, const void* d_Cp, int64_t ldc, 
     return set_error(SHIRO_ERR_INVALID_ARG, "aggregate_c: NULL pointer");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   return launch_aggregate_c(plan, tuning_for(plan, SHIRO_KERNEL_SPMM, N, in_dt), d_Cp, ldc, N, in_dt, d_Y, ldy,
-                            out_dt, s);
+                            out_dt, (flags & SHIRO_AGG_ACCUMULATE) != 0, s);
+}
+
+SHIRO_API int shiro_mvc_bipartite(int64_t n_left, int64_t n_right, int64_t n_edges, const int32_t* h_left,
+                                  const int32_t* h_right, const int64_t* h_w_left, const int64_t* h_w_right,
+                                  uint8_t* h_cover_left, uint8_t* h_cover_right, int64_t* h_weight) {
+  if (n_left < 0 || n_right < 0 || n_edges < 0 || n_left + n_right > (1 << 30))
+    return set_error(SHIRO_ERR_INVALID_ARG, "mvc_bipartite: bad sizes");
+  if (!h_weight || (n_left > 0 && !h_cover_left) || (n_right > 0 && !h_cover_right) ||
+      (n_edges > 0 && (!h_left || !h_right)))
+    return set_error(SHIRO_ERR_INVALID_ARG, "mvc_bipartite: NULL pointer");
+  for (int64_t e = 0; e < n_edges; ++e)
+    if (h_left[e] < 0 || h_left[e] >= n_left || h_right[e] < 0 || h_right[e] >= n_right)
+      return set_error(SHIRO_ERR_INVALID_ARG, "mvc_bipartite: edge endpoint out of range");
+  for (int64_t i = 0; h_w_left && i < n_left; ++i)
+    if (h_w_left[i] < 0) return set_error(SHIRO_ERR_INVALID_ARG, "mvc_bipartite: negative weight");
+  for (int64_t j = 0; h_w_right && j < n_right; ++j)
+    if (h_w_right[j] < 0) return set_error(SHIRO_ERR_INVALID_ARG, "mvc_bipartite: negative weight");
+  return solve_mvc(n_left, n_right, n_edges, h_left, h_right, h_w_left, h_w_right, h_cover_left,
+                   h_cover_right, h_weight);
+}
+
+SHIRO_API int shiro_joint_plan(shiro_plan plan, const int64_t* h_w_row, const int64_t* h_w_col, uint8_t* h_assign,
+                               int64_t* h_stats, int32_t n_threads, shiro_stream_t stream) {
+  if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "joint_plan: plan is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (stream_capturing(s)) return set_error(SHIRO_ERR_CAPTURING, "joint_plan: stream is capturing");
+  for (int64_t i = 0; h_w_row && i < plan->rows; ++i)
+    if (h_w_row[i] < 0) return set_error(SHIRO_ERR_INVALID_ARG, "joint_plan: negative row cost");
+  for (int64_t j = 0; h_w_col && j < plan->n_cols; ++j)
+    if (h_w_col[j] < 0) return set_error(SHIRO_ERR_INVALID_ARG, "joint_plan: negative column cost");
+  return joint_plan(plan, h_w_row, h_w_col, h_assign, h_stats, n_threads, s);
 }
 
 SHIRO_API int shiro_prepare(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t ops,
@@ -783,11 +863,11 @@ SHIRO_API int shiro_autotune(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_
     SHIRO_TRY(dev_alloc(&b.dB, plan->n_cols * N * sz));
     SHIRO_TRY(launch_fill_random((float*)b.dB, plan->n_cols * N * sz / 4, 4, s));
   }
-  SHIRO_TRY(dev_alloc_n(&b.vals, plan->nz_begin + nnz));
-  SHIRO_TRY(dev_alloc_n(&b.dvals, plan->nz_begin + nnz));
+  SHIRO_TRY(dev_alloc_n(&b.vals, plan->nz_begin + plan->src_nnz));
+  SHIRO_TRY(dev_alloc_n(&b.dvals, plan->nz_begin + plan->src_nnz));
   SHIRO_TRY(launch_fill_random((float*)b.Bp, U * N * sz / 4, 1, s));
   SHIRO_TRY(launch_fill_random((float*)b.dY, R * N * sz / 4, 2, s));
-  SHIRO_TRY(launch_fill_random(b.vals, plan->nz_begin + nnz, 3, s));
+  SHIRO_TRY(launch_fill_random(b.vals, plan->nz_begin + plan->src_nnz, 3, s));
   if (ops & SHIRO_OP_BACKWARD) SHIRO_TRY(build_transposed(plan, s));
   if (ops & SHIRO_OP_SPMM) SHIRO_TRY(tune_one(plan, SHIRO_KERNEL_SPMM, N, dt, b, s));
   if (ops & SHIRO_OP_BACKWARD) {

@@ -61,6 +61,7 @@ struct RowBased {
   int64_t* agg_ptr = nullptr;   // rows + 1: each panel row's entries
   int32_t* agg_idx = nullptr;   // R: entry position of each (row, block) pair, blocks ascending
   float* ones = nullptr;        // R: unit weights of the sum
+  int32_t* iota = nullptr;      // rows: identity row map (sum added into Y)
   float* vals = nullptr;        // nnz: values in block-major order (per call)
   int64_t* block_off = nullptr; // P + 1: first entry of each block
 };
@@ -84,6 +85,12 @@ struct shiro_plan_s {
   // pattern (library-owned copies)
   int64_t* row_ptr = nullptr;  // rows + 1, rebased to 0
   int32_t* col = nullptr;      // nnz
+  // subset plans (a chosen part of the panel's nonzeros): the position of
+  // each nonzero among the panel's src_nnz nonzeros, by which the caller's
+  // values are read; NULL for a whole panel (src_nnz == nnz)
+  int32_t* vmap = nullptr;     // nnz
+  float* svals = nullptr;      // nnz: values in the subset's order (per call)
+  int64_t src_nnz = 0;
 
   // selection
   bool selected = false;
@@ -173,6 +180,13 @@ int build_worklist(const int64_t* ptr, int64_t R, int64_t nnz, int32_t chunk, Wo
 int build_transposed(shiro_plan plan, hipStream_t s);
 int build_segments(shiro_plan plan, hipStream_t s);
 int build_rowbased(shiro_plan plan, hipStream_t s);
+// Joint row-column strategy (host): minimum weighted vertex cover of one
+// bipartite graph, and the per-panel plan over its off-diagonal blocks.
+int solve_mvc(int64_t n_left, int64_t n_right, int64_t n_edges, const int32_t* left,
+              const int32_t* right, const int64_t* w_left, const int64_t* w_right,
+              uint8_t* cover_left, uint8_t* cover_right, int64_t* weight);
+int joint_plan(shiro_plan plan, const int64_t* w_row, const int64_t* w_col, uint8_t* assign,
+               int64_t* stats, int32_t n_threads, hipStream_t s);
 // Row-based scheme: the owner's partial C rows over B (global rows), and
 // their sum into the panel's rows.
 int launch_partial_c(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* B,
@@ -180,7 +194,14 @@ int launch_partial_c(shiro_plan plan, const shiro_tuning_t& t, const float* vals
                      shiro_dtype out_dt, hipStream_t s);
 int launch_aggregate_c(shiro_plan plan, const shiro_tuning_t& t, const void* Cp, int64_t ldc,
                        int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy, shiro_dtype out_dt,
-                       hipStream_t s);
+                       bool accumulate, hipStream_t s);
+// Subset plans: keep flags -> compacted pattern and value map; composition
+// of a permutation with the value map.
+int launch_subset(const int64_t* row_ptr_src, int64_t rows, int64_t nz0, int64_t nnz_panel,
+                  const int32_t* col_src, const uint8_t* keep, uint8_t keep_val, int64_t* pos,
+                  int32_t* col_out, int32_t* vmap, int64_t* row_ptr_out, void* scan_tmp,
+                  hipStream_t s);
+int launch_compose(int32_t* perm, const int32_t* vmap, int64_t n, hipStream_t s);
 int ensure_rb_work(shiro_plan plan, int32_t chunk, bool allocate, hipStream_t s,
                    const WorkList** rb, const WorkList** agg);
 

@@ -267,6 +267,66 @@ int launch_block_nnz(const int32_t* col, int64_t nnz, int64_t K, int32_t P, int6
   return SHIRO_OK;
 }
 
+namespace {
+struct KeepIn {
+  const uint8_t* keep;
+  uint8_t v;
+  __device__ int64_t operator()(int64_t k) const { return keep[k] == v ? 1 : 0; }
+};
+struct PosOut {
+  int64_t* pos;
+  __device__ void operator()(int64_t k, int64_t prefix, int64_t) const { pos[k] = prefix; }
+};
+
+// Kept nonzero k of the panel goes to position pos[k] of the subset.
+__global__ void k_subset_compact(const int32_t* __restrict__ col, const uint8_t* __restrict__ keep, uint8_t v,
+                                 const int64_t* __restrict__ pos, int64_t n, int32_t* __restrict__ col_out,
+                                 int32_t* __restrict__ vmap) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x)
+    if (keep[k] == v) {
+      col_out[pos[k]] = col[k];
+      vmap[pos[k]] = (int32_t)k;
+    }
+}
+
+// Subset row pointers: kept nonzeros before each row start.
+__global__ void k_subset_rowptr(const int64_t* __restrict__ row_ptr_src, int64_t rows, int64_t nz0,
+                                const int64_t* __restrict__ pos, int64_t* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= rows;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = pos[row_ptr_src[i] - nz0];
+}
+
+__global__ void k_compose(int32_t* __restrict__ perm, const int32_t* __restrict__ vmap, int64_t n) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x)
+    perm[j] = vmap[perm[j]];
+}
+}  // namespace
+
+// pos must hold nnz_panel + 1 entries (pos[nnz_panel] = kept count).
+int launch_subset(const int64_t* row_ptr_src, int64_t rows, int64_t nz0, int64_t nnz_panel,
+                  const int32_t* col_src, const uint8_t* keep, uint8_t keep_val, int64_t* pos,
+                  int32_t* col_out, int32_t* vmap, int64_t* row_ptr_out, void* scan_tmp,
+                  hipStream_t s) {
+  SHIRO_TRY(scan_generic(KeepIn{keep, keep_val}, nnz_panel, PosOut{pos}, pos + nnz_panel, scan_tmp, s));
+  if (nnz_panel > 0) {
+    k_subset_compact<<<grid_for(nnz_panel), kBlock, 0, s>>>(col_src, keep, keep_val, pos, nnz_panel, col_out, vmap);
+    SHIRO_LAUNCH_CHECK();
+  }
+  k_subset_rowptr<<<grid_for(rows + 1), kBlock, 0, s>>>(row_ptr_src, rows, nz0, pos, row_ptr_out);
+  SHIRO_LAUNCH_CHECK();
+  return SHIRO_OK;
+}
+
+int launch_compose(int32_t* perm, const int32_t* vmap, int64_t n, hipStream_t s) {
+  if (n <= 0) return SHIRO_OK;
+  k_compose<<<grid_for(n), kBlock, 0, s>>>(perm, vmap, n);
+  SHIRO_LAUNCH_CHECK();
+  return SHIRO_OK;
+}
+
 int launch_zero_bytes(uint8_t* p, int64_t n, hipStream_t s) {
   if (n <= 0) return SHIRO_OK;
   k_zero_bytes<<<grid_for(ceil_div(n, 16), 16384), kBlock, 0, s>>>(p, n);

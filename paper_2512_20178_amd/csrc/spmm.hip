@@ -544,6 +544,7 @@ struct SddmmArgs {
   const void* Bp;
   int64_t ldp;
   float* dvals;
+  const int32_t* out_map;  // optional: dvals index of each pattern nonzero (subset plans)
   const int32_t* chunk_row;
   const int32_t* chunk_nz;
   int32_t W, R, N;
@@ -555,8 +556,8 @@ template <typename TIN, int LANES, int VEC, int UNROLL>
 __global__ __launch_bounds__(kBlock) void k_sddmm(
     const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx, const TIN* __restrict__ dY,
     int64_t lddy, const TIN* __restrict__ Bp, int64_t ldp, float* __restrict__ dvals,
-    const int32_t* __restrict__ chunk_row, const int32_t* __restrict__ chunk_nz, int32_t W, int32_t R,
-    int32_t N, int32_t cpw, int32_t xcd_remap) {
+    const int32_t* __restrict__ out_map, const int32_t* __restrict__ chunk_row,
+    const int32_t* __restrict__ chunk_nz, int32_t W, int32_t R, int32_t N, int32_t cpw, int32_t xcd_remap) {
   constexpr int G = kWave / LANES;
   constexpr int TW = LANES * VEC;
   constexpr int STEP = G * UNROLL;
@@ -622,7 +623,7 @@ __global__ __launch_bounds__(kBlock) void k_sddmm(
         for (int u = 0; u < UNROLL; ++u) {
           part[u] = group_sum<LANES>(part[u]);
           const int64_t kk = k + u * G + g;
-          if (li == LANES - 1 && kk < ke) dvals[kk] = part[u];
+          if (li == LANES - 1 && kk < ke) dvals[out_map ? (int64_t)out_map[kk] : kk] = part[u];
         }
       }
     }
@@ -942,8 +943,8 @@ int sddmm_dispatch(const shiro_tuning_t& t, dim3 grid, hipStream_t s, const Sddm
   if (t.lanes == L && t.unroll == U) {                                                      \
     k_sddmm<TIN, L, VEC, U><<<grid, kBlock, 0, s>>>(                                        \
         a.ptr, a.idx, reinterpret_cast<const TIN*>(a.dY), a.lddy,                           \
-        reinterpret_cast<const TIN*>(a.Bp), a.ldp, a.dvals, a.chunk_row, a.chunk_nz, a.W,   \
-        a.R, a.N, a.chunks_per_wave, a.xcd_remap);                                          \
+        reinterpret_cast<const TIN*>(a.Bp), a.ldp, a.dvals, a.out_map, a.chunk_row,         \
+        a.chunk_nz, a.W, a.R, a.N, a.chunks_per_wave, a.xcd_remap);                         \
     SHIRO_LAUNCH_CHECK();                                                                   \
     return SHIRO_OK;                                                                        \
   }
@@ -1116,6 +1117,8 @@ int build_transposed(shiro_plan plan, hipStream_t s) {
                                                        nnz, plan->row_ptr, plan->rows, U, tr.row,
                                                        tr.ptr);
   SHIRO_LAUNCH_CHECK();
+  // subset plans read the caller's values through the value map
+  if (plan->vmap) SHIRO_TRY(launch_compose(tr.perm, plan->vmap, nnz, s));
   SHIRO_HIP(hipStreamSynchronize(s));
   tr.built = true;
   return SHIRO_OK;
@@ -1235,15 +1238,22 @@ namespace {
 int launch_pattern(shiro_plan plan, const shiro_tuning_t& t, const WorkList* wl, const int64_t* ptr,
                    const int32_t* idx, const float* vals, int64_t R, const void* X, int64_t ldx,
                    int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy, shiro_dtype out_dt,
-                   hipStream_t s) {
+                   hipStream_t s, const int32_t* add_rows = nullptr) {
   SpmmArgs a{};
   a.ptr = ptr;
   a.idx = idx;
   a.vals = vals;
   a.X = X;
   a.ldx = ldx;
-  a.out = Y;
-  a.ldo = ldy;
+  if (add_rows) {  // Y[add_rows[r]] += the sum of row r
+    a.scat = Y;
+    a.lds = ldy;
+    a.scat_idx = add_rows;
+    a.scat_mode = 1;
+  } else {
+    a.out = Y;
+    a.ldo = ldy;
+  }
   a.chunk_row = wl->chunk_row;
   a.chunk_nz = wl->chunk_nz;
   a.carry = plan->carry;
@@ -1266,6 +1276,15 @@ int launch_pattern(shiro_plan plan, const shiro_tuning_t& t, const WorkList* wl,
 }
 }  // namespace
 
+// The plan's values in its own nonzero order: the caller's array at the
+// panel's offset, or (subset plans) gathered through the value map.
+static const float* plan_values(shiro_plan plan, const float* vals, hipStream_t s) {
+  const float* v = vals + plan->nz_begin;
+  if (!plan->vmap || plan->nnz == 0) return v;
+  k_gather_vals<<<grid_for(plan->nnz), kBlock, 0, s>>>(plan->vmap, v, plan->nnz, plan->svals);
+  return plan->svals;
+}
+
 int launch_spmm(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* X,
                 int64_t ldx, int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy,
                 shiro_dtype out_dt, hipStream_t s) {
@@ -1273,8 +1292,10 @@ int launch_spmm(shiro_plan plan, const shiro_tuning_t& t, const float* vals, con
   const WorkList* wl;
   SHIRO_TRY(ensure_rows_work(plan, t.chunk, !stream_capturing(s), s, &wl));
   SHIRO_TRY(ensure_carry(plan, (int64_t)wl->W * 2 * N, !stream_capturing(s)));
-  return launch_pattern(plan, t, wl, plan->row_ptr, plan->colmap, vals + plan->nz_begin, plan->rows, X,
-                        ldx, N, in_dt, Y, ldy, out_dt, s);
+  const float* v = plan_values(plan, vals, s);
+  SHIRO_LAUNCH_CHECK();
+  return launch_pattern(plan, t, wl, plan->row_ptr, plan->colmap, v, plan->rows, X, ldx, N, in_dt, Y, ldy,
+                        out_dt, s);
 }
 
 int build_rowbased(shiro_plan plan, hipStream_t s) {
@@ -1293,6 +1314,11 @@ int build_rowbased(shiro_plan plan, hipStream_t s) {
   SHIRO_TRY(dev_alloc_n(&rb.ones, std::max<int64_t>(R, 1)));
   SHIRO_TRY(dev_alloc_n(&rb.vals, std::max<int64_t>(nnz, 1)));
   SHIRO_TRY(dev_alloc_n(&rb.block_off, (int64_t)P + 1));
+  SHIRO_TRY(dev_alloc_n(&rb.iota, std::max<int64_t>(rows, 1)));
+  if (rows > 0) {
+    k_iota<<<grid_for(rows), kBlock, 0, s>>>(reinterpret_cast<uint32_t*>(rb.iota), rows);
+    SHIRO_LAUNCH_CHECK();
+  }
   SHIRO_HIP(hipMemcpyAsync(rb.block_off, sg.h_off.data(), (size_t)(P + 1) * 8, hipMemcpyHostToDevice, s));
   // the block-major copy: entry j covers nonzeros [ptr[j], ptr[j+1])
   SHIRO_TRY(ensure_scratch(plan, scan_scratch_bytes(std::max<int64_t>(R, 1)) + (std::max<int64_t>(R, 1) * 4 + 256)));
@@ -1303,6 +1329,7 @@ int build_rowbased(shiro_plan plan, hipStream_t s) {
   if (nnz > 0 && R > 0) {
     k_rb_fill<<<grid_for(nnz), kBlock, 0, s>>>(rb.ptr, R, sg.seg_begin, plan->col, nnz, rb.perm, rb.col);
     SHIRO_LAUNCH_CHECK();
+    if (plan->vmap) SHIRO_TRY(launch_compose(rb.perm, plan->vmap, nnz, s));
     k_rb_agg<<<grid_for(R), kBlock, 0, s>>>(sg.seg_csr, sg.seg_row, R, rb.agg_idx, row_csr, rb.ones);
     SHIRO_LAUNCH_CHECK();
   }
@@ -1330,7 +1357,7 @@ int launch_partial_c(shiro_plan plan, const shiro_tuning_t& t, const float* vals
 
 int launch_aggregate_c(shiro_plan plan, const shiro_tuning_t& t, const void* Cp, int64_t ldc,
                        int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy, shiro_dtype out_dt,
-                       hipStream_t s) {
+                       bool accumulate, hipStream_t s) {
   const RowBased& rb = plan->rb;
   if (plan->rows == 0 || N == 0) return SHIRO_OK;
   const bool cap = stream_capturing(s);
@@ -1338,7 +1365,7 @@ int launch_aggregate_c(shiro_plan plan, const shiro_tuning_t& t, const void* Cp,
   SHIRO_TRY(ensure_rb_work(plan, t.chunk, !cap, s, &wl, &wa));
   SHIRO_TRY(ensure_carry(plan, (int64_t)std::max(wl->W, wa->W) * 2 * N, !cap));
   return launch_pattern(plan, t, wa, rb.agg_ptr, rb.agg_idx, rb.ones, plan->rows, Cp, ldc, N, in_dt, Y, ldy,
-                        out_dt, s);
+                        out_dt, s, accumulate ? rb.iota : nullptr);
 }
 
 int launch_spmm_t(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* dY,
@@ -1416,6 +1443,7 @@ int launch_sddmm(shiro_plan plan, const shiro_tuning_t& t, const float*, const v
   a.Bp = Bp;
   a.ldp = ldp;
   a.dvals = dvals + plan->nz_begin;
+  a.out_map = plan->vmap;  // subset plans write through the value map
   a.chunk_row = wl->chunk_row;
   a.chunk_nz = wl->chunk_nz;
   a.W = wl->W;
@@ -1441,6 +1469,7 @@ int launch_sddmm(shiro_plan plan, const shiro_tuning_t& t, const float*, const v
 int launch_spmm_per_block(shiro_plan plan, const float* vals, const void* X, int64_t ldx,
                           int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy, shiro_dtype out_dt,
                           hipStream_t s) {
+  if (plan->vmap) return set_error(SHIRO_ERR_UNSUPPORTED, "per-block mode is not available on subset plans");
   if (plan->rows == 0 || N == 0) return SHIRO_OK;
   if (!plan->seg.built) {
     if (stream_capturing(s))

@@ -108,3 +108,48 @@ def test_set_allocator_arguments(lib):
     assert lib.shiro_set_allocator(keep, _lib.FREE_FN(), None) == -1
     assert "both" in _err(lib)
     assert lib.shiro_set_allocator(_lib.ALLOC_FN(), _lib.FREE_FN(), None) == 0  # back to hipMalloc
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_mvc_bipartite_matches_oracle(seed):
+    """The library's host max-flow cover against the oracle's (same minimum
+    cost; the returned set must be a cover of exactly that cost)."""
+    import numpy as np
+
+    import oracle
+    import paper_2512_20178_amd as shiro
+
+    rng = np.random.default_rng(100 + seed)
+    nl, nr = int(rng.integers(1, 300)), int(rng.integers(1, 300))
+    mask = rng.random((nl, nr)) < rng.uniform(0.002, 0.05)
+    if seed == 0:
+        mask[:] = False  # no edges: empty cover
+    edges = np.argwhere(mask)
+    weighted = seed % 3 == 2
+    wl = rng.integers(0, 20, nl) if weighted else None
+    wr = rng.integers(0, 20, nr) if weighted else None
+    mu, cl, cr = shiro.mvc_bipartite(nl, nr, edges[:, 0], edges[:, 1], wl, wr)
+    ref, _, _ = oracle.mvc_bipartite(nl, nr, edges, wl, wr)
+    assert mu == ref
+    cl, cr = cl.numpy(), cr.numpy()
+    assert all(cl[i] or cr[j] for i, j in edges)
+    wlv = np.ones(nl, np.int64) if wl is None else wl
+    wrv = np.ones(nr, np.int64) if wr is None else wr
+    assert mu == int(wlv[cl].sum() + wrv[cr].sum())
+
+
+def test_mvc_bipartite_argument_errors(lib):
+    import ctypes as c
+
+    w = c.c_int64()
+    left = (c.c_int32 * 1)(5)
+    right = (c.c_int32 * 1)(0)
+    cl = (c.c_uint8 * 2)()
+    cr = (c.c_uint8 * 2)()
+    assert lib.shiro_mvc_bipartite(2, 2, 1, left, right, None, None, cl, cr, c.byref(w)) == -1
+    assert "out of range" in _err(lib)
+    neg = (c.c_int64 * 2)(1, -1)
+    left[0] = 1
+    assert lib.shiro_mvc_bipartite(2, 2, 1, left, right, neg, None, cl, cr, c.byref(w)) == -1
+    assert "negative" in _err(lib)
+    assert lib.shiro_mvc_bipartite(-1, 2, 0, None, None, None, None, cl, cr, c.byref(w)) == -1

@@ -12,6 +12,7 @@ import torch
 
 import oracle
 import synth
+from conftest import load_golden
 
 pytestmark = pytest.mark.gpu
 
@@ -448,6 +449,103 @@ def test_row_based_graph_replays(shiro, run):
         run.plan.replay(gid[0], stream=cs)
         cs.synchronize()
         assert torch.equal(Y, ref)
+
+
+# ----------------------------------------------------------------------------
+# joint row-column strategy: per-block minimum covers, subset plans, forward
+# ----------------------------------------------------------------------------
+def _assign_cover(Ac, assign, q):
+    """(rows sent row-based, columns fetched column-based) of block q under an assignment."""
+    nz0, n = Ac.nz_begin, Ac.nnz_panel
+    rows = np.repeat(np.arange(Ac.M), np.diff(Ac.row_ptr[Ac.row_begin:Ac.row_end + 1]))
+    cols = Ac.col[nz0:nz0 + n]
+    m = (cols // Ac.K) == q
+    a = assign[m]
+    return set(rows[m][a == 1].tolist()), set(cols[m][a == 0].tolist())
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_joint_plan_matches_oracle(shiro, run, weighted):
+    rng = np.random.default_rng(8)
+    w_row = rng.integers(1, 6, run.Ac.M) if weighted else None
+    w_col = rng.integers(1, 6, run.A.n_cols) if weighted else None
+    assign, stats = shiro.joint_plan(run.plan, w_row, w_col)
+    assign, stats = assign.numpy(), stats.numpy()
+    ref = oracle.joint_cover(run.Ac, w_row, w_col)
+    rs, roff = oracle.select_c_rows(run.Ac)
+    for q in range(run.A.P):
+        assert stats[q, 1] == roff[q + 1] - roff[q] and stats[q, 2] == run.off[q + 1] - run.off[q]
+        rows, cols = _assign_cover(run.Ac, assign, q)
+        if ref[q] is None:  # the diagonal block stays column-based
+            assert stats[q, 0] == 0 and not rows
+            continue
+        mu = ref[q][0]
+        assert stats[q, 0] == mu
+        wr = np.ones(run.Ac.M, np.int64) if w_row is None else w_row
+        wc = np.ones(run.A.n_cols, np.int64) if w_col is None else w_col
+        # the assignment realises a cover of the optimal cost
+        assert sum(int(wr[i]) for i in rows) + sum(int(wc[j]) for j in cols) <= mu
+        assert stats[q, 3] == len(rows)
+
+
+def test_joint_plan_fig1(shiro):
+    g = load_golden("fig1_block01.txt")
+    n, P, p = g["n"][0][0], g["P"][0][0], g["p"][0][0]
+    mask = np.zeros((n, n))
+    for r, c, v in g["nz"]:
+        mask[r, c] = v
+    A = synth.from_dense_pattern(mask, P=P, p=p)
+    Ad = A.to(torch.device("cuda"))
+    plan = shiro.partition(Ad.row_ptr, Ad.col, A.n_rows, A.n_cols, A.P, A.p)
+    assign, stats = shiro.joint_plan(plan)
+    (q, mu), = g["expect_joint_cover_block"]
+    assert int(stats[q, 0]) == mu
+    # b, c, d (row 0) go row-based; f, h are covered by fetching b_6
+    assert assign.tolist() == [1, 1, 1, 0, 0]
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_joint_forward(shiro, run, dtype):
+    A = run.A
+    js = shiro.JointSpMM(run.Ad.row_ptr, run.Ad.col, A.n_rows, A.n_cols, A.P, A.p)
+    assert js.U + js.R >= int(js.stats[:, 0].sum())  # volumes before and after planning
+    B = run.B.to(dtype).to(run.dev)
+    Y = js.forward(run.Ad.vals, B)
+    Yref, den = _fwd_ref(run, run.B.numpy())
+    tol = TOL_F32 if dtype == torch.float32 else TOL_BF16
+    assert oracle.rel_err(bf16_to_f32(Y), Yref, den) <= tol
+    if dtype == torch.float32:
+        assert torch.equal(js.forward(run.Ad.vals, B), Y)  # reproducible
+
+
+def test_subset_plan_backward(shiro, run):
+    """A column-based subset plan: A_col^T dY and dvals through the value map."""
+    A, Ac = run.A, run.Ac
+    js = shiro.JointSpMM(run.Ad.row_ptr, run.Ad.col, A.n_rows, A.n_cols, A.P, A.p)
+    keep = js.assign.numpy() == 0
+    nz0 = Ac.nz_begin
+    # host CSR of the column-based part: the panel's kept nonzeros, other rows empty
+    rows = np.repeat(np.arange(Ac.M), np.diff(Ac.row_ptr[Ac.row_begin:Ac.row_end + 1]))[keep]
+    counts = np.zeros(Ac.n_rows, np.int64)
+    counts[Ac.row_begin:Ac.row_end] = np.bincount(rows, minlength=Ac.M)
+    rp = np.concatenate([[0], np.cumsum(counts)])
+    Acol = oracle.Csr(Ac.n_rows, Ac.n_cols, rp, Ac.col[nz0:nz0 + Ac.nnz_panel][keep],
+                      Ac.vals[nz0:nz0 + Ac.nnz_panel][keep], Ac.P, Ac.p)
+    uc, off, cm = oracle.select(Acol)
+    assert js.U == len(uc)
+    Bp = shiro.pack_B(js.col_plan, run.B.to(run.dev))
+    dY = run.G.to(run.dev)
+    dBp = torch.empty(js.U, run.N, device=run.dev)
+    dvals = torch.full((A.nnz,), -5.0, device=run.dev)
+    shiro.spmm_backward(js.col_plan, run.Ad.vals, dY, Bp, dBpacked=dBp, dvals=dvals)
+    ref = oracle.spmm_t(Acol, run.G.numpy(), cm, n_out=len(uc))
+    rden = oracle.spmm_t(Acol, run.G.numpy(), cm, n_out=len(uc), abs_mode=True)
+    assert oracle.rel_err(dBp.cpu().numpy(), ref, rden) <= TOL_F32
+    dv = dvals.cpu().numpy()[nz0:nz0 + Ac.nnz_panel]
+    full = oracle.sddmm(Ac, run.G.numpy(), run.B.numpy(), None)
+    fden = oracle.sddmm(Ac, run.G.numpy(), run.B.numpy(), None, abs_mode=True)
+    assert oracle.rel_err(dv[keep], full[keep], fden[keep]) <= TOL_F32
+    assert bool((dv[~keep] == -5.0).all())  # the row-based nonzeros are not touched
 
 
 def test_torch_allocator(shiro):
