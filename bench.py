@@ -333,6 +333,32 @@ def main():
                             "aggregate_c_us": round(t_ag, 2), "forward_us": round(t_pc + t_ag, 2)}
         log(f"row-based: {out['row_based']}")
         del Cp
+        # the joint row-column strategy (Sec. 5): per-block minimum covers
+        # planned on the host, then the column-based part through select /
+        # pack / spmm and the row-based part through partial / sum (volumes
+        # of Sec. 5.4 Eq. V_joint against V_col and V_row, off-diagonal)
+        out["joint"] = None  # one block: nothing off the diagonal to plan
+        if A.P > 1:
+            t = time.perf_counter()
+            js = shiro.JointSpMM(A.row_ptr, A.col, A.n_rows, A.n_cols, A.P, A.p)
+            t_plan = time.perf_counter() - t
+            st = js.stats.numpy()
+            off = np.arange(A.P) != A.p
+            mu = int(st[off, 0].sum())
+            js.prepare(N, tdt)
+            Yj = torch.empty(M, N, dtype=tdt, device=dev)
+            Bpj = torch.empty(js.U, N, dtype=tdt, device=dev)
+            Cpj = torch.empty(js.R, N, dtype=tdt, device=dev)
+            t_joint = timed(lambda: js.forward(vals, B, out=Yj, Bp=Bpj, Cp=Cpj))
+            rows_off, cols_off = int(st[off, 1].sum()), int(st[off, 2].sum())
+            out["joint"] = {"mu_offdiag": mu, "rows_offdiag": rows_off, "cols_offdiag": cols_off,
+                            "red_col": round(1 - mu / cols_off, 4) if cols_off else None,
+                            "red_row": round(1 - mu / rows_off, 4) if rows_off else None,
+                            "v_joint_bytes": mu * N * sz, "plan_s": round(t_plan, 2),
+                            "col_part_nnz": int(js.col_plan.info()["nnz"]),
+                            "row_part_nnz": int(js.row_plan.info()["nnz"]), "forward_us": round(t_joint, 2)}
+            log(f"joint: {out['joint']}")
+            del js, Yj, Bpj, Cpj
         if tdt == torch.bfloat16:
             # BF16 storage in, FP32 output
             Y32 = torch.empty(M, N, dtype=torch.float32, device=dev)

@@ -341,8 +341,10 @@ SHIRO_API int shiro_joint_plan(shiro_plan plan, const int64_t* h_w_row, const in
                                shiro_stream_t stream);
 
 /* Build everything the per-call steps need for (N, dtype, ops) - work lists,
- * transposed pattern, carry buffers - so later calls neither allocate nor
- * synchronise (required before graph capture).  Synchronises the stream. */
+ * transposed pattern, row-based structures, carry buffers - so later calls
+ * neither allocate nor synchronise (required before graph capture).  Ops
+ * other than SHIRO_OP_ROW_BASED need shiro_select_rows first (NOT_READY).
+ * Synchronises the stream. */
 SHIRO_API int shiro_prepare(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t ops,
                             shiro_stream_t stream);
 

@@ -807,7 +807,8 @@ SHIRO_API int shiro_joint_plan(shiro_plan plan, const int64_t* h_w_row, const in
 SHIRO_API int shiro_prepare(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t ops,
                             shiro_stream_t stream) {
   if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "prepare: plan is NULL");
-  if (!plan->selected) return set_error(SHIRO_ERR_NOT_READY, "prepare: call shiro_select_rows first");
+  if ((ops & ~SHIRO_OP_ROW_BASED) && !plan->selected)
+    return set_error(SHIRO_ERR_NOT_READY, "prepare: call shiro_select_rows first");
   if (!valid_dt(dt) || N < 1) return set_error(SHIRO_ERR_INVALID_ARG, "prepare: bad N or dtype");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (stream_capturing(s)) return set_error(SHIRO_ERR_CAPTURING, "prepare: stream is capturing");

@@ -509,6 +509,7 @@ def test_joint_forward(shiro, run, dtype):
     A = run.A
     js = shiro.JointSpMM(run.Ad.row_ptr, run.Ad.col, A.n_rows, A.n_cols, A.P, A.p)
     assert js.U + js.R >= int(js.stats[:, 0].sum())  # volumes before and after planning
+    js.prepare(run.N, dtype)
     B = run.B.to(dtype).to(run.dev)
     Y = js.forward(run.Ad.vals, B)
     Yref, den = _fwd_ref(run, run.B.numpy())
