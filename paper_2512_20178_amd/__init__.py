@@ -34,6 +34,7 @@ __all__ = [
     "aggregate_c",
     "partition_subset",
     "JointSpMM",
+    "JointSpMMFunction",
     "mvc_bipartite",
     "joint_plan",
     "prepare",
@@ -355,10 +356,12 @@ class JointSpMM:
         self.row_plan = partition_subset(row_ptr, col, n_rows, n_cols, P, p, keep, 1)
         self.U, self.Uq = select_rows(self.col_plan)
         self.R, self.Rq = select_c_rows(self.row_plan)
+        # the row-based part's own column selection serves its backward
+        self.U_row, _ = select_rows(self.row_plan)
 
-    def prepare(self, N: int, dtype=torch.float32):
-        prepare(self.col_plan, N, dtype, ops=("spmm",))
-        prepare(self.row_plan, N, dtype, ops=("row_based",))
+    def prepare(self, N: int, dtype=torch.float32, backward: bool = False):
+        prepare(self.col_plan, N, dtype, ops=("spmm", "backward") if backward else ("spmm",))
+        prepare(self.row_plan, N, dtype, ops=("row_based", "backward") if backward else ("row_based",))
 
     def forward(self, vals: torch.Tensor, B: torch.Tensor, out: Optional[torch.Tensor] = None,
                 Bp: Optional[torch.Tensor] = None, Cp: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
@@ -366,6 +369,40 @@ class JointSpMM:
         Y = spmm(self.col_plan, vals, Bp, out=out, stream=stream)
         Cp = partial_c(self.row_plan, vals, B, self.R, out=Cp, stream=stream)
         return aggregate_c(self.row_plan, Cp, out=Y, accumulate=True, stream=stream)
+
+    def backward(self, vals: torch.Tensor, B: torch.Tensor, dY: torch.Tensor, dB: Optional[torch.Tensor] = None,
+                 dvals: Optional[torch.Tensor] = None, stream=None):
+        """Gradients of <dY, Y> with Y = forward(vals, B): dB (zero-filled, the
+        shape of B) and dvals (float32 like vals, the panel's entries).  The
+        column-based part writes its columns' rows of dB, the row-based part
+        adds its own; each part gives the value gradients of its nonzeros."""
+        if dB is None:
+            dB = torch.zeros_like(B)
+        if dvals is None:
+            dvals = torch.zeros_like(vals)
+        Bp = pack_B(self.col_plan, B, stream=stream)
+        spmm_backward(self.col_plan, vals, dY, Bp, None, dB, dvals, stream=stream, dB_overwrite=True)
+        if self.R > 0:
+            Bpr = pack_B(self.row_plan, B, stream=stream)
+            spmm_backward(self.row_plan, vals, dY, Bpr, None, dB, dvals, stream=stream)
+        return dB, dvals
+
+
+class JointSpMMFunction(torch.autograd.Function):
+    """Y = A^(p,:) B through the joint strategy, with gradients for the values
+    and for B (the backward of JointSpMM)."""
+
+    @staticmethod
+    def forward(ctx, vals, B, js):
+        ctx.js = js
+        ctx.save_for_backward(vals, B)
+        return js.forward(vals, B)
+
+    @staticmethod
+    def backward(ctx, dY):
+        vals, B = ctx.saved_tensors
+        dB, dvals = ctx.js.backward(vals, B, dY.to(B.dtype).contiguous())
+        return (dvals if ctx.needs_input_grad[0] else None), (dB if ctx.needs_input_grad[1] else None), None
 
 
 # ---------------------------------------------------------------------------

@@ -519,6 +519,27 @@ def test_joint_forward(shiro, run, dtype):
         assert torch.equal(js.forward(run.Ad.vals, B), Y)  # reproducible
 
 
+def test_joint_backward_and_autograd(shiro, run):
+    A, Ac = run.A, run.Ac
+    js = shiro.JointSpMM(run.Ad.row_ptr, run.Ad.col, A.n_rows, A.n_cols, A.P, A.p)
+    B = run.B.to(run.dev)
+    dY = run.G.to(run.dev)
+    dB, dvals = js.backward(run.Ad.vals, B, dY)
+    rdB = oracle.spmm_t(Ac, run.G.numpy(), None)
+    rden = oracle.spmm_t(Ac, run.G.numpy(), None, abs_mode=True)
+    assert oracle.rel_err(dB.cpu().numpy(), rdB, np.maximum(rden, 0)) <= TOL_F32
+    nz0 = Ac.nz_begin
+    rdv = oracle.sddmm(Ac, run.G.numpy(), run.B.numpy(), None)
+    rdvd = oracle.sddmm(Ac, run.G.numpy(), run.B.numpy(), None, abs_mode=True)
+    assert oracle.rel_err(dvals.cpu().numpy()[nz0:nz0 + Ac.nnz_panel], rdv, rdvd) <= TOL_F32
+    # through autograd: the same gradients
+    vp = run.Ad.vals.clone().requires_grad_(True)
+    Bg = B.clone().requires_grad_(True)
+    Y = shiro.JointSpMMFunction.apply(vp, Bg, js)
+    Y.backward(dY)
+    assert torch.equal(Bg.grad, dB) and torch.equal(vp.grad, dvals)
+
+
 def test_subset_plan_backward(shiro, run):
     """A column-based subset plan: A_col^T dY and dvals through the value map."""
     A, Ac = run.A, run.Ac
