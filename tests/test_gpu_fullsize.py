@@ -156,6 +156,34 @@ def test_rmat24_spmm_and_backward_sampled(shiro, rmat24):
     del dB
 
 
+def test_rmat24_row_based_and_joint_sampled(shiro, rmat24):
+    """The row-based scheme and the joint strategy at full size, as the
+    benchmark runs them: Rows per block bit-exact against the oracle, the
+    joint covers' costs against the oracle's min-cut, and sampled rows of
+    both products."""
+    plan, B, N, Ac, A = rmat24["plan"], rmat24["B"], rmat24["N"], rmat24["Ac"], rmat24["A"]
+    dev = B.device
+    R, Rq = shiro.select_c_rows(plan)
+    rs, roff = oracle.select_c_rows(Ac)
+    grs, goff = shiro.c_row_selection(plan, R)
+    assert np.array_equal(grs.cpu().numpy(), rs) and np.array_equal(goff.cpu().numpy(), roff)
+    rows = sample_rows(Ac)
+    Bh = B.cpu().numpy()
+    yref = oracle.spmm_rows(Ac, rows, Bh, None)
+    den = oracle.spmm_rows(Ac, rows, Bh, None, abs_mode=True)
+    ri = torch.from_numpy(rows).to(dev)
+    Y = shiro.aggregate_c(plan, shiro.partial_c(plan, A.vals, B, R))
+    assert oracle.rel_err(Y[ri].cpu().numpy(), yref, den) <= TOL_F32
+    js = shiro.JointSpMM(A.row_ptr, A.col, A.n_rows, A.n_cols, A.P, A.p)
+    st = js.stats.numpy()
+    ref = oracle.joint_cover(Ac)
+    for q in range(A.P):  # every off-diagonal block (q = p is the diagonal one)
+        assert st[q, 0] == (0 if ref[q] is None else ref[q][0])
+    js.prepare(N)
+    Yj = js.forward(A.vals, B)
+    assert oracle.rel_err(Yj[ri].cpu().numpy(), yref, den) <= TOL_F32
+
+
 # ----------------------------------------------------------------------------
 # Erdos-Renyi panel, every dense width of the N sweep
 # ----------------------------------------------------------------------------
