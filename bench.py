@@ -323,6 +323,8 @@ def main():
         t = time.perf_counter()
         R, Rq = shiro.select_c_rows(plan)
         t_rsel = time.perf_counter() - t
+        if not args.no_autotune:
+            shiro.autotune(plan, N, tdt, ops=("row_based",))
         shiro.prepare(plan, N, tdt, ops=("row_based",))
         Cp = torch.empty(R, N, dtype=tdt, device=dev)
         t_pc = timed(lambda: shiro.partial_c(plan, vals, B, R, out=Cp))
@@ -345,6 +347,9 @@ def main():
             st = js.stats.numpy()
             off = np.arange(A.P) != A.p
             mu = int(st[off, 0].sum())
+            if not args.no_autotune:
+                shiro.autotune(js.col_plan, N, tdt, ops=("spmm",))
+                shiro.autotune(js.row_plan, N, tdt, ops=("row_based",))
             js.prepare(N, tdt)
             Yj = torch.empty(M, N, dtype=tdt, device=dev)
             Bpj = torch.empty(js.U, N, dtype=tdt, device=dev)

@@ -129,7 +129,8 @@ typedef struct {
   int64_t U;              /* sum_q |Cols(A^(p,q))|, -1 before select_rows     */
 } shiro_plan_info_t;
 
-/* Tuning knobs of one kernel family (spmm, transposed spmm or sddmm). */
+/* Tuning knobs of one kernel family (spmm, transposed spmm, sddmm, or the
+ * row-based scheme's partial rows and sum). */
 typedef struct {
   int32_t chunk;     /* merge-path items (rows + nonzeros) per wavefront       */
   int32_t lanes;     /* lanes sharing one dense row: 8, 16, 32 or 64 (tile width = lanes * 16 bytes) */
@@ -142,6 +143,8 @@ typedef struct {
 #define SHIRO_KERNEL_SPMM 0
 #define SHIRO_KERNEL_SPMM_T 1
 #define SHIRO_KERNEL_SDDMM 2
+#define SHIRO_KERNEL_PARTIAL_C 3   /* row-based scheme: the owner's partial rows */
+#define SHIRO_KERNEL_AGGREGATE_C 4 /* row-based scheme: their sum into the panel */
 
 /* Library version, 10000*major + 100*minor + patch. */
 SHIRO_API int shiro_version(void);
@@ -352,7 +355,9 @@ SHIRO_API int shiro_prepare(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t
  * plan's shape at width N and keep the fastest per kernel in the plan (the
  * median of nine runs ranks each candidate).  The backward is tuned in the
  * form autograd uses (dB rows overwritten, plus dvals), on a scratch dB of
- * n_cols x N.  If the environment variable SHIRO_TUNE_CACHE names a file,
+ * n_cols x N; SHIRO_OP_ROW_BASED tunes the row-based partial rows (on a
+ * scratch B of n_cols x N) and their sum.  If the environment variable
+ * SHIRO_TUNE_CACHE names a file,
  * results are read from it (no timing for keys it holds) and new results are
  * appended (one line per key).  Allocates and synchronises. */
 SHIRO_API int shiro_autotune(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t ops,

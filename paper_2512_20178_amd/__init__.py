@@ -48,7 +48,8 @@ __all__ = [
 ]
 
 _DT = {torch.float32: _lib.F32, torch.bfloat16: _lib.BF16}
-_KERNELS = {"spmm": _lib.KERNEL_SPMM, "spmm_t": _lib.KERNEL_SPMM_T, "sddmm": _lib.KERNEL_SDDMM}
+_KERNELS = {"spmm": _lib.KERNEL_SPMM, "spmm_t": _lib.KERNEL_SPMM_T, "sddmm": _lib.KERNEL_SDDMM,
+            "partial_c": _lib.KERNEL_PARTIAL_C, "aggregate_c": _lib.KERNEL_AGGREGATE_C}
 
 
 def _L():

@@ -42,6 +42,8 @@ OP_ROW_BASED = 8
 KERNEL_SPMM = 0
 KERNEL_SPMM_T = 1
 KERNEL_SDDMM = 2
+KERNEL_PARTIAL_C = 3
+KERNEL_AGGREGATE_C = 4
 
 CHECK_CSR = 1
 

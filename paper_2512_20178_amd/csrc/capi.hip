@@ -132,22 +132,20 @@ int ensure_rows_work(shiro_plan plan, int32_t chunk, bool allocate, hipStream_t 
   return SHIRO_OK;
 }
 
-int ensure_rb_work(shiro_plan plan, int32_t chunk, bool allocate, hipStream_t s,
-                   const WorkList** rb, const WorkList** agg) {
-  for (int which = 0; which < 2; ++which) {
-    auto& m = which == 0 ? plan->rb_work : plan->agg_work;
-    auto it = m.find(chunk);
-    if (it == m.end()) {
-      if (!allocate)
-        return set_error(SHIRO_ERR_CAPTURING,
-                         "row-based work list for chunk " + std::to_string(chunk) + " not prepared before capture");
-      WorkList wl;
-      if (which == 0) SHIRO_TRY(build_worklist(plan->rb.ptr, plan->rb.R, plan->nnz, chunk, &wl, s));
-      else SHIRO_TRY(build_worklist(plan->rb.agg_ptr, plan->rows, plan->rb.R, chunk, &wl, s));
-      it = m.emplace(chunk, wl).first;
-    }
-    *(which == 0 ? rb : agg) = &it->second;
+int ensure_rb_work(shiro_plan plan, int which, int32_t chunk, bool allocate, hipStream_t s,
+                   const WorkList** out) {
+  auto& m = which == 0 ? plan->rb_work : plan->agg_work;
+  auto it = m.find(chunk);
+  if (it == m.end()) {
+    if (!allocate)
+      return set_error(SHIRO_ERR_CAPTURING,
+                       "row-based work list for chunk " + std::to_string(chunk) + " not prepared before capture");
+    WorkList wl;
+    if (which == 0) SHIRO_TRY(build_worklist(plan->rb.ptr, plan->rb.R, plan->nnz, chunk, &wl, s));
+    else SHIRO_TRY(build_worklist(plan->rb.agg_ptr, plan->rows, plan->rb.R, chunk, &wl, s));
+    it = m.emplace(chunk, wl).first;
   }
+  *out = &it->second;
   return SHIRO_OK;
 }
 
@@ -203,18 +201,20 @@ int ensure_tvals(shiro_plan plan, bool allocate) {
 // chunks, one nonzero in flight per lane group (high occupancy wins for
 // these gather-bound loops), 8 workgroups per CU.
 shiro_tuning_t default_tuning(int kernel, int32_t, shiro_dtype) {
+  const bool row_based = kernel == SHIRO_KERNEL_PARTIAL_C || kernel == SHIRO_KERNEL_AGGREGATE_C;
   shiro_tuning_t t;
   t.chunk = 128;
   t.lanes = 64;
   t.unroll = kernel == SHIRO_KERNEL_SPMM ? 1 : 2;
-  t.group_rows = 0;
+  t.group_rows = row_based ? 1 : 0;  // the partial rows' segments are short
   t.xcd_remap = 0;
-  t.wg_per_cu = kernel == SHIRO_KERNEL_SPMM_T ? 16 : 8;
+  t.wg_per_cu = (kernel == SHIRO_KERNEL_SPMM_T || row_based) ? 16 : 8;
   return t;
 }
 
 int validate_tuning(int kernel, int32_t, shiro_dtype, const shiro_tuning_t& t) {
-  if (kernel < 0 || kernel > 2) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: unknown kernel family");
+  if (kernel < 0 || kernel > SHIRO_KERNEL_AGGREGATE_C)
+    return set_error(SHIRO_ERR_INVALID_ARG, "tuning: unknown kernel family");
   if (t.chunk < 16 || t.chunk > (1 << 22)) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: chunk outside [16, 2^22]");
   if (t.lanes != 8 && t.lanes != 16 && t.lanes != 32 && t.lanes != 64)
     return set_error(SHIRO_ERR_INVALID_ARG, "tuning: lanes must be 8, 16, 32 or 64");
@@ -294,6 +294,7 @@ struct TuneBuffers {
   void* dY = nullptr;
   void* dBp = nullptr;
   void* dB = nullptr;
+  void* Cp = nullptr;
   float* vals = nullptr;
   float* dvals = nullptr;
   ~TuneBuffers() {
@@ -302,6 +303,7 @@ struct TuneBuffers {
     dev_free(dY);
     dev_free(dBp);
     dev_free(dB);
+    dev_free(Cp);
     dev_free(vals);
     dev_free(dvals);
   }
@@ -388,6 +390,10 @@ static int tune_one(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt, Tune
     if (kernel == SHIRO_KERNEL_SPMM_T)  // the form autograd uses: dB rows overwritten, and dvals
       return launch_spmm_t(plan, t, b.vals, b.dY, N, N, dt, nullptr, 0, b.dB, N, true, b.Bp, N,
                            b.dvals, nullptr, s);
+    if (kernel == SHIRO_KERNEL_PARTIAL_C)  // scratch B of n_cols x N
+      return launch_partial_c(plan, t, b.vals, b.dB, N, N, dt, b.Cp, N, dt, s);
+    if (kernel == SHIRO_KERNEL_AGGREGATE_C)
+      return launch_aggregate_c(plan, t, b.Cp, N, N, dt, b.Y, N, dt, false, s);
     return launch_sddmm(plan, t, b.vals, b.dY, N, b.Bp, N, N, dt, b.dvals, s);
   };
   shiro_tuning_t best = default_tuning(kernel, N, dt);
@@ -753,8 +759,8 @@ SHIRO_API int shiro_partial_c(shiro_plan plan, const float* d_vals, const void* 
   if (N > 0 && plan->rb.R > 0 && (!d_vals || !d_B || !d_Cp))
     return set_error(SHIRO_ERR_INVALID_ARG, "partial_c: NULL pointer");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  return launch_partial_c(plan, tuning_for(plan, SHIRO_KERNEL_SPMM, N, in_dt), d_vals, d_B, ldb, N, in_dt, d_Cp,
-                          ldc, out_dt, s);
+  return launch_partial_c(plan, tuning_for(plan, SHIRO_KERNEL_PARTIAL_C, N, in_dt), d_vals, d_B, ldb, N, in_dt,
+                          d_Cp, ldc, out_dt, s);
 }
 
 SHIRO_API int shiro_aggregate_c(shiro_plan plan, const void* d_Cp, int64_t ldc, int32_t N, shiro_dtype in_dt,
@@ -769,8 +775,8 @@ SHIRO_API int shiro_aggregate_c(shiro_plan plan, const void* d_Cp, int64_t ldc, 
   if (N > 0 && plan->rows > 0 && (!d_Y || (plan->rb.R > 0 && !d_Cp)))
     return set_error(SHIRO_ERR_INVALID_ARG, "aggregate_c: NULL pointer");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  return launch_aggregate_c(plan, tuning_for(plan, SHIRO_KERNEL_SPMM, N, in_dt), d_Cp, ldc, N, in_dt, d_Y, ldy,
-                            out_dt, (flags & SHIRO_AGG_ACCUMULATE) != 0, s);
+  return launch_aggregate_c(plan, tuning_for(plan, SHIRO_KERNEL_AGGREGATE_C, N, in_dt), d_Cp, ldc, N, in_dt, d_Y,
+                            ldy, out_dt, (flags & SHIRO_AGG_ACCUMULATE) != 0, s);
 }
 
 SHIRO_API int shiro_mvc_bipartite(int64_t n_left, int64_t n_right, int64_t n_edges, const int32_t* h_left,
@@ -829,10 +835,12 @@ SHIRO_API int shiro_prepare(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t
   }
   if (ops & SHIRO_OP_ROW_BASED) {
     SHIRO_TRY(build_rowbased(plan, s));
-    const shiro_tuning_t t = tuning_for(plan, SHIRO_KERNEL_SPMM, N, dt);
-    const WorkList *wr, *wa;
-    SHIRO_TRY(ensure_rb_work(plan, t.chunk, true, s, &wr, &wa));
-    SHIRO_TRY(ensure_carry(plan, (int64_t)std::max(wr->W, wa->W) * 2 * N, true));
+    for (int which = 0; which < 2; ++which) {
+      const shiro_tuning_t t =
+          tuning_for(plan, which == 0 ? SHIRO_KERNEL_PARTIAL_C : SHIRO_KERNEL_AGGREGATE_C, N, dt);
+      SHIRO_TRY(ensure_rb_work(plan, which, t.chunk, true, s, &wl));
+      SHIRO_TRY(ensure_carry(plan, (int64_t)wl->W * 2 * N, true));
+    }
   }
   if (ops & SHIRO_OP_PER_BLOCK) {
     SHIRO_TRY(build_segments(plan, s));
@@ -859,10 +867,16 @@ SHIRO_API int shiro_autotune(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_
   SHIRO_TRY(dev_alloc(&b.Y, R * N * 4));
   SHIRO_TRY(dev_alloc(&b.dY, R * N * 4));
   SHIRO_TRY(dev_alloc(&b.dBp, U * N * 4));
-  if (ops & SHIRO_OP_BACKWARD) {
-    // scratch dB of the full B shape (only the selected rows are touched)
+  if (ops & (SHIRO_OP_BACKWARD | SHIRO_OP_ROW_BASED)) {
+    // scratch of the full B shape: dB of the backward (only the selected rows
+    // are touched), B of the row-based partial rows
     SHIRO_TRY(dev_alloc(&b.dB, plan->n_cols * N * sz));
     SHIRO_TRY(launch_fill_random((float*)b.dB, plan->n_cols * N * sz / 4, 4, s));
+  }
+  if (ops & SHIRO_OP_ROW_BASED) {
+    SHIRO_TRY(build_rowbased(plan, s));
+    SHIRO_TRY(dev_alloc(&b.Cp, std::max<int64_t>(plan->rb.R, 1) * N * 4));
+    SHIRO_TRY(launch_fill_random((float*)b.Cp, std::max<int64_t>(plan->rb.R, 1) * N * sz / 4, 5, s));
   }
   SHIRO_TRY(dev_alloc_n(&b.vals, plan->nz_begin + plan->src_nnz));
   SHIRO_TRY(dev_alloc_n(&b.dvals, plan->nz_begin + plan->src_nnz));
@@ -875,6 +889,10 @@ SHIRO_API int shiro_autotune(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_
     SHIRO_TRY(tune_one(plan, SHIRO_KERNEL_SPMM_T, N, dt, b, s));
     SHIRO_TRY(tune_one(plan, SHIRO_KERNEL_SDDMM, N, dt, b, s));
   }
+  if (ops & SHIRO_OP_ROW_BASED) {
+    SHIRO_TRY(tune_one(plan, SHIRO_KERNEL_PARTIAL_C, N, dt, b, s));
+    SHIRO_TRY(tune_one(plan, SHIRO_KERNEL_AGGREGATE_C, N, dt, b, s));
+  }
   SHIRO_HIP(hipStreamSynchronize(s));
   return shiro_prepare(plan, N, dt, ops, stream);
 }
@@ -882,7 +900,8 @@ SHIRO_API int shiro_autotune(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_
 SHIRO_API int shiro_get_tuning(shiro_plan plan, int32_t kernel, int32_t N, shiro_dtype dt,
                                shiro_tuning_t* h_tuning) {
   if (!plan || !h_tuning) return set_error(SHIRO_ERR_INVALID_ARG, "get_tuning: NULL argument");
-  if (kernel < 0 || kernel > 2) return set_error(SHIRO_ERR_INVALID_ARG, "get_tuning: unknown kernel family");
+  if (kernel < 0 || kernel > SHIRO_KERNEL_AGGREGATE_C)
+    return set_error(SHIRO_ERR_INVALID_ARG, "get_tuning: unknown kernel family");
   *h_tuning = tuning_for(plan, kernel, N, dt);
   return SHIRO_OK;
 }

@@ -202,8 +202,9 @@ int launch_subset(const int64_t* row_ptr_src, int64_t rows, int64_t nz0, int64_t
                   int32_t* col_out, int32_t* vmap, int64_t* row_ptr_out, void* scan_tmp,
                   hipStream_t s);
 int launch_compose(int32_t* perm, const int32_t* vmap, int64_t n, hipStream_t s);
-int ensure_rb_work(shiro_plan plan, int32_t chunk, bool allocate, hipStream_t s,
-                   const WorkList** rb, const WorkList** agg);
+// which = 0: the partial rows' work list, 1: the sum's.
+int ensure_rb_work(shiro_plan plan, int which, int32_t chunk, bool allocate, hipStream_t s,
+                   const WorkList** out);
 
 int launch_pack(shiro_plan plan, const void* B, int64_t ldb, int32_t N, shiro_dtype dt,
                 void* Bp, int64_t ldp, hipStream_t s);

@@ -1346,9 +1346,9 @@ int launch_partial_c(shiro_plan plan, const shiro_tuning_t& t, const float* vals
   const RowBased& rb = plan->rb;
   if (rb.R == 0 || N == 0) return SHIRO_OK;
   const bool cap = stream_capturing(s);
-  const WorkList *wl, *wa;
-  SHIRO_TRY(ensure_rb_work(plan, t.chunk, !cap, s, &wl, &wa));
-  SHIRO_TRY(ensure_carry(plan, (int64_t)std::max(wl->W, wa->W) * 2 * N, !cap));
+  const WorkList* wl;
+  SHIRO_TRY(ensure_rb_work(plan, 0, t.chunk, !cap, s, &wl));
+  SHIRO_TRY(ensure_carry(plan, (int64_t)wl->W * 2 * N, !cap));
   // values in block-major order (they may change from call to call)
   k_gather_vals<<<grid_for(plan->nnz), kBlock, 0, s>>>(rb.perm, vals + plan->nz_begin, plan->nnz, rb.vals);
   SHIRO_LAUNCH_CHECK();
@@ -1361,9 +1361,9 @@ int launch_aggregate_c(shiro_plan plan, const shiro_tuning_t& t, const void* Cp,
   const RowBased& rb = plan->rb;
   if (plan->rows == 0 || N == 0) return SHIRO_OK;
   const bool cap = stream_capturing(s);
-  const WorkList *wl, *wa;
-  SHIRO_TRY(ensure_rb_work(plan, t.chunk, !cap, s, &wl, &wa));
-  SHIRO_TRY(ensure_carry(plan, (int64_t)std::max(wl->W, wa->W) * 2 * N, !cap));
+  const WorkList* wa;
+  SHIRO_TRY(ensure_rb_work(plan, 1, t.chunk, !cap, s, &wa));
+  SHIRO_TRY(ensure_carry(plan, (int64_t)wa->W * 2 * N, !cap));
   return launch_pattern(plan, t, wa, rb.agg_ptr, rb.agg_idx, rb.ones, plan->rows, Cp, ldc, N, in_dt, Y, ldy,
                         out_dt, s, accumulate ? rb.iota : nullptr);
 }

@@ -247,6 +247,16 @@ def test_backward_bf16(shiro, run):
     mask[torch.from_numpy(run.uc).long()] = False
     assert torch.equal(dB2.cpu()[~mask], dB.cpu()[~mask])
     assert bool((dB2.cpu()[mask] == 1).all())
+    # the group kernel in bfloat16 (lanes below one tile are raised to it)
+    for lanes in (8, 16, 32):
+        shiro.set_tuning(run.plan, "spmm_t", run.N, torch.bfloat16, lanes=lanes, group_rows=1, chunk=64, unroll=2)
+        dB3 = torch.zeros_like(dB)
+        dvals3 = torch.zeros_like(dvals)
+        shiro.spmm_backward(run.plan, run.Ad.vals, Gh.to(dev), Bp, dB=dB3, dvals=dvals3, dB_overwrite=True)
+        assert oracle.rel_err(bf16_to_f32(dB3)[run.uc], rdBp, rden) <= TOL_BF16
+        gv3 = dvals3.cpu().numpy()[run.Ac.nz_begin:run.Ac.nz_begin + run.Ac.nnz_panel]
+        assert oracle.rel_err(gv3, rdv, rdv_den) <= TOL_BF16
+    shiro.set_tuning(run.plan, "spmm_t", run.N, torch.bfloat16, lanes=64, group_rows=0, chunk=128, unroll=2)
 
 
 @pytest.mark.parametrize("knobs", [
@@ -380,6 +390,13 @@ def test_autotune_then_correct(shiro, monkeypatch, tmp_path):
     assert oracle.rel_err(Y.cpu().numpy(), Yref, den) <= TOL_F32
     lines = (tmp_path / "tune.txt").read_text().splitlines()
     assert len(lines) == 3 and all(ln.split()[0].endswith(("|k=0", "|k=1", "|k=2")) for ln in lines)
+    # the row-based scheme's two kernels
+    shiro.autotune(plan, N, torch.float32, ops=("row_based",))
+    lines = (tmp_path / "tune.txt").read_text().splitlines()
+    assert len(lines) == 5 and lines[3].split()[0].endswith("|k=3") and lines[4].split()[0].endswith("|k=4")
+    R, _ = shiro.select_c_rows(plan)
+    Yr = shiro.aggregate_c(plan, shiro.partial_c(plan, Ad.vals, B, R))
+    assert oracle.rel_err(Yr.cpu().numpy(), Yref, den) <= TOL_F32
 
 
 # ----------------------------------------------------------------------------
