@@ -220,7 +220,10 @@ int validate_tuning(int kernel, int32_t, shiro_dtype, const shiro_tuning_t& t) {
     return set_error(SHIRO_ERR_INVALID_ARG, "tuning: lanes must be 8, 16, 32 or 64");
   if (t.unroll != 1 && t.unroll != 2 && t.unroll != 4)
     return set_error(SHIRO_ERR_INVALID_ARG, "tuning: unroll must be 1, 2 or 4");
-  if (t.group_rows != 0 && t.group_rows != 1) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: group_rows must be 0 or 1");
+  if (t.group_rows < 0 || t.group_rows > 2) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: group_rows must be 0, 1 or 2");
+  if (t.group_rows == 2 && kernel != SHIRO_KERNEL_SPMM_T && kernel != SHIRO_KERNEL_PARTIAL_C)
+    return set_error(SHIRO_ERR_INVALID_ARG,
+                     "tuning: group_rows 2 (nonzero walk) needs rows without gaps: transposed product or partial rows only");
   if (t.xcd_remap != 0 && t.xcd_remap != 1) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: xcd_remap must be 0 or 1");
   if (t.wg_per_cu < 1 || t.wg_per_cu > 32) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: wg_per_cu outside [1, 32]");
   return SHIRO_OK;
@@ -265,6 +268,7 @@ static void plan_free(shiro_plan plan) {
   dev_free(plan->tr.ptr);
   dev_free(plan->tr.row);
   dev_free(plan->tr.perm);
+  dev_free(plan->tr.rid);
   dev_free(plan->seg.seg_row);
   dev_free(plan->seg.seg_begin);
   dev_free(plan->seg.seg_end);
@@ -272,6 +276,7 @@ static void plan_free(shiro_plan plan) {
   dev_free(plan->rb.ptr);
   dev_free(plan->rb.col);
   dev_free(plan->rb.perm);
+  dev_free(plan->rb.rid);
   dev_free(plan->rb.agg_ptr);
   dev_free(plan->rb.agg_idx);
   dev_free(plan->rb.ones);
@@ -418,7 +423,8 @@ static int tune_one(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt, Tune
     }
   // stage 2: lane width, occupancy, XCD placement around the best
   const shiro_tuning_t base = best;
-  for (int grp : {0, 1})
+  const bool walk = kernel == SHIRO_KERNEL_SPMM_T || kernel == SHIRO_KERNEL_PARTIAL_C;
+  for (int grp = 0; grp <= (walk ? 2 : 1); ++grp)
     for (int lanes : {64, 32, 16})
       for (int wg : {4, 8, 16})
         for (int xcd : {0, 1}) {

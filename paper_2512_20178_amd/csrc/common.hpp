@@ -152,6 +152,15 @@ struct Elem<float> {
     }
   }
   template <int VEC>
+  __device__ __forceinline__ static void store_nt(float* p, const float (&v)[VEC]) {
+    if constexpr (VEC == 4) {
+      f32x4 w = {v[0], v[1], v[2], v[3]};
+      __builtin_nontemporal_store(w, reinterpret_cast<f32x4*>(p));
+    } else {
+      store<VEC>(p, v);
+    }
+  }
+  template <int VEC>
   __device__ __forceinline__ static void store(float* p, const float (&v)[VEC]) {
     if constexpr (VEC % 4 == 0) {
 #pragma unroll
@@ -189,7 +198,30 @@ struct Elem<bf16_t> {
   }
   template <int VEC>
   __device__ __forceinline__ static void load_nt(const bf16_t* p, float (&o)[VEC]) {
-    load<VEC>(p, o);
+    if constexpr (VEC == 8) {
+      u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+      uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        o[2 * e] = __uint_as_float(w[e] << 16);
+        o[2 * e + 1] = __uint_as_float(w[e] & 0xffff0000u);
+      }
+    } else {
+      load<VEC>(p, o);
+    }
+  }
+  template <int VEC>
+  __device__ __forceinline__ static void store_nt(bf16_t* p, const float (&v)[VEC]) {
+    if constexpr (VEC == 8) {
+      uint32_t w[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        w[e] = (uint32_t)f32_to_bf16(v[2 * e]) | ((uint32_t)f32_to_bf16(v[2 * e + 1]) << 16);
+      u32x4 o = {w[0], w[1], w[2], w[3]};
+      __builtin_nontemporal_store(o, reinterpret_cast<u32x4*>(p));
+    } else {
+      store<VEC>(p, v);
+    }
   }
   template <int VEC>
   __device__ __forceinline__ static void store(bf16_t* p, const float (&v)[VEC]) {

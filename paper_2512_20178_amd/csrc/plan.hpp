@@ -34,6 +34,7 @@ struct Transposed {
   int64_t* ptr = nullptr;   // U + 1
   int32_t* row = nullptr;   // nnz: panel row of each entry
   int32_t* perm = nullptr;  // nnz: CSR position of each entry (value index)
+  int32_t* rid = nullptr;   // nnz: transposed row (packed column) of each entry
 };
 
 // Per-block row segments for the one-launch-per-block mode.
@@ -58,6 +59,7 @@ struct RowBased {
   int64_t* ptr = nullptr;       // R + 1: each entry's nonzeros in the block-major copy
   int32_t* col = nullptr;       // nnz: global column id of each nonzero, block-major
   int32_t* perm = nullptr;      // nnz: CSR position of each nonzero, block-major
+  int32_t* rid = nullptr;       // nnz: entry of each nonzero, block-major
   int64_t* agg_ptr = nullptr;   // rows + 1: each panel row's entries
   int32_t* agg_idx = nullptr;   // R: entry position of each (row, block) pair, blocks ascending
   float* ones = nullptr;        // R: unit weights of the sum

@@ -118,6 +118,7 @@ struct SpmmArgs {
   const int32_t* scat_idx;  // R
   const int32_t* chunk_row;  // W + 1
   const int32_t* chunk_nz;   // W + 1
+  const int32_t* rid;       // nnz: row of each nonzero (only for patterns without empty rows)
   float* carry;             // [W][2][N]
   int32_t W, R, N;
   int32_t chunks_per_wave;
@@ -131,14 +132,14 @@ struct SpmmArgs {
       const TIN *__restrict__ X, int64_t ldx, TOUT *__restrict__ out, int64_t ldo,           \
       TOUT *__restrict__ scat, int64_t lds, const int32_t *__restrict__ scat_idx,             \
       const int32_t *__restrict__ chunk_row, const int32_t *__restrict__ chunk_nz,            \
-      float *__restrict__ carry, int32_t W, int32_t R, int32_t N, int32_t cpw, int32_t xcd_remap, \
-      int32_t scat_mode
+      const int32_t *__restrict__ rid, float *__restrict__ carry, int32_t W, int32_t R,         \
+      int32_t N, int32_t cpw, int32_t xcd_remap, int32_t scat_mode
 
 #define SHIRO_SPMM_ARGS(TIN, TOUT, a)                                                          \
   (a).ptr, (a).idx, (a).vals, reinterpret_cast<const TIN*>((a).D), (a).ldd, (a).dot_out,      \
       reinterpret_cast<const TIN*>((a).X), (a).ldx,                                            \
       reinterpret_cast<TOUT*>((a).out), (a).ldo, reinterpret_cast<TOUT*>((a).scat), (a).lds,   \
-      (a).scat_idx, (a).chunk_row, (a).chunk_nz, (a).carry, (a).W, (a).R, (a).N,               \
+      (a).scat_idx, (a).chunk_row, (a).chunk_nz, (a).rid, (a).carry, (a).W, (a).R, (a).N,     \
       (a).chunks_per_wave, (a).xcd_remap, (a).scat_mode
 
 template <typename TOUT, int VEC>
@@ -445,6 +446,147 @@ __global__ __launch_bounds__(kBlock) void k_spmm_grp(SHIRO_SPMM_PARAMS(TIN, TOUT
       rs = rsn;
       re = ren;
     }
+  }
+}
+
+// Variant for patterns whose rows are all non-empty and mostly hold one or
+// two nonzeros (the transposed pattern, one row per selected column; the
+// row-based scheme's partial rows).  Lane group g of a wavefront owns whole
+// chunks and walks their nonzeros UNROLL at a time without regard to row
+// boundaries, so it keeps UNROLL dense rows in flight even where every row
+// holds a single nonzero.  rid[k] is the row of nonzero k; a row's sum is
+// written when the walk reaches a nonzero of another row or the chunk's end.
+// Rows cut by the chunk's ends go to its carry slots as in k_spmm: the first
+// row's piece (empty or not) when that row began in an earlier chunk, the
+// last row's piece when the chunk holds any of it.  A group's chunks are
+// consecutive, so its nonzeros form one contiguous run and each step's
+// indices are loaded one step ahead, across chunk ends too.  Sums inside a
+// row keep pattern order, so results stay reproducible.  Rows written once
+// (the output, the overwritten dB rows) and the dense rows D read once are
+// marked non-temporal, so they do not push the gathered rows out of the
+// caches (on the 2^24 R-MAT panel this took the transposed product without
+// dvals from 469 to 344 us).
+template <typename TIN, typename TOUT, int LANES, int VEC, int UNROLL, bool DOT, int SCAT>
+__global__ __launch_bounds__(kBlock) void k_spmm_flat(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
+  constexpr int G = kWave / LANES;
+  const int lane = lane_id();
+  const int g = lane / LANES;
+  const int li = lane % LANES;
+  const int64_t c = (int64_t)blockIdx.y * (LANES * VEC) + (int64_t)li * VEC;
+  const bool cvalid = c < N;
+  const int64_t cl = cvalid ? c : 0;
+
+  const int64_t worker = (int64_t)uniform(logical_block(xcd_remap) * kWavesPerBlock + wave_id()) * G + g;
+  const int64_t wb = worker * cpw;
+  const int64_t we = wb + cpw < W ? wb + cpw : W;
+  if (wb >= we) return;  // whole lane groups leave; the others use no cross-group lane ops
+  const int64_t kend = chunk_nz[we];
+  int32_t xi[UNROLL], ri[UNROLL];
+  float v[UNROLL];
+  if (chunk_nz[wb] < kend) {
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const int64_t kk = chunk_nz[wb] + u;
+      const int64_t kc = kk < kend ? kk : kend - 1;
+      xi[u] = idx[kc];
+      ri[u] = rid[kc];
+      v[u] = vals[kc];
+    }
+  }
+  for (int64_t w = wb; w < we; ++w) {
+    const int32_t i0 = chunk_row[w], i1 = chunk_row[w + 1];
+    const int64_t j0 = chunk_nz[w], j1 = chunk_nz[w + 1];
+    if (i0 >= R) break;
+    const bool has_head = j0 > ptr[i0];
+    float* const head_slot = carry + (w * 2) * N + c;
+    float* const tail_slot = carry + (w * 2 + 1) * N + c;
+    if (has_head && ptr[i0 + 1] <= j0 && cvalid) {  // row i0 holds nothing here
+      float z[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) z[e] = 0.f;
+      Elem<float>::template store<VEC>(head_slot, z);
+    }
+    int32_t cur = -1, scur = 0;  // open row and its scatter row
+    float acc[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
+    auto flush = [&]() {
+      if (!cvalid) return;
+      if (cur == i0 && has_head) {
+        Elem<float>::template store<VEC>(head_slot, acc);
+      } else if (cur == i1) {
+        Elem<float>::template store<VEC>(tail_slot, acc);
+      } else {
+        if (out) Elem<TOUT>::template store_nt<VEC>(out + (int64_t)cur * ldo + c, acc);
+        if constexpr (SCAT == 1) {
+          float pre[VEC];
+          Elem<TOUT>::template load<VEC>(scat + (int64_t)scur * lds + c, pre);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) pre[e] += acc[e];
+          Elem<TOUT>::template store<VEC>(scat + (int64_t)scur * lds + c, pre);
+        } else if constexpr (SCAT == 2) {
+          Elem<TOUT>::template store_nt<VEC>(scat + (int64_t)scur * lds + c, acc);
+        }
+      }
+    };
+    for (int64_t k = j0; k < j1; k += UNROLL) {
+      bool ok[UNROLL];
+      float x[UNROLL][VEC];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        ok[u] = k + u < j1;
+        Elem<TIN>::template load<VEC>(X + (int64_t)xi[u] * ldx + cl, x[u]);
+      }
+      float d[DOT ? UNROLL : 1][VEC];  // lanes past N read column 0; their dots are masked below
+      if constexpr (DOT) {
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) Elem<TIN>::template load_nt<VEC>(D + (int64_t)ri[u] * ldd + cl, d[u]);
+      }
+      int32_t sc[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) sc[u] = SCAT ? scat_idx[ri[u]] : 0;
+      // the next step: the rest of this chunk, else the next chunk's start
+      const int64_t kn = k + UNROLL < j1 ? k + UNROLL : j1;
+      int32_t xin[UNROLL], rin[UNROLL];
+      float vn[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const int64_t kk = kn + u;
+        const int64_t kc = kk < kend ? kk : kend - 1;
+        xin[u] = idx[kc];
+        rin[u] = rid[kc];
+        vn[u] = vals[kc];
+      }
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        if (ok[u] && ri[u] != cur) {
+          if (cur >= 0) flush();
+          cur = ri[u];
+          scur = sc[u];
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
+        }
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const float t = fmaf(v[u], x[u][e], acc[e]);
+          acc[e] = ok[u] ? t : acc[e];
+        }
+        if constexpr (DOT) {
+          float q = 0.f;
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) q = fmaf(d[u][e], x[u][e], q);
+          q = group_sum<LANES>(cvalid ? q : 0.f);
+          if (li == LANES - 1 && ok[u]) dot_out[k + u] = q;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        xi[u] = xin[u];
+        ri[u] = rin[u];
+        v[u] = vn[u];
+      }
+    }
+    if (cur >= 0) flush();
   }
 }
 
@@ -833,7 +975,7 @@ unsigned grid_for(int64_t n, int64_t cap = 65536) {
 // ptr[j+1]), its CSR position and its global column id.
 __global__ void k_rb_fill(const int64_t* __restrict__ ptr, int64_t R, const int32_t* __restrict__ seg_begin,
                           const int32_t* __restrict__ col, int64_t nnz, int32_t* __restrict__ perm,
-                          int32_t* __restrict__ col_bm) {
+                          int32_t* __restrict__ col_bm, int32_t* __restrict__ rid) {
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nnz;
        t += (int64_t)gridDim.x * blockDim.x) {
     int64_t lo = 0, hi = R - 1;  // last j with ptr[j] <= t
@@ -844,6 +986,7 @@ __global__ void k_rb_fill(const int64_t* __restrict__ ptr, int64_t R, const int3
     const int32_t k = seg_begin[lo] + (int32_t)(t - ptr[lo]);
     perm[t] = k;
     col_bm[t] = col[k];
+    rid[t] = (int32_t)lo;
   }
 }
 
@@ -922,7 +1065,9 @@ template <typename TIN, typename TOUT, int VEC, bool DOT, int SCAT>
 int spmm_dispatch(const shiro_tuning_t& t, dim3 grid, hipStream_t s, const SpmmArgs& a) {
 #define SHIRO_SPMM_CASE(L, U)                                                                          \
   if (t.lanes == L && t.unroll == U) {                                                                 \
-    if (t.group_rows)                                                                                  \
+    if (t.group_rows == 2 && a.rid)                                                                    \
+      k_spmm_flat<TIN, TOUT, L, VEC, U, DOT, SCAT><<<grid, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a)); \
+    else if (t.group_rows)                                                                             \
       k_spmm_grp<TIN, TOUT, L, VEC, U, DOT, SCAT><<<grid, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a)); \
     else                                                                                               \
       k_spmm<TIN, TOUT, L, VEC, U, DOT, SCAT><<<grid, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a));     \
@@ -969,7 +1114,9 @@ int run_spmm_family(shiro_plan plan, shiro_tuning_t t, const WorkList* wl, SpmmA
                     hipStream_t s) {
   t.lanes = effective_lanes(t.lanes, a.N, vec);
   unsigned nb;
-  SHIRO_TRY(grid_waves(plan, t, wl->W, kWavesPerBlock, &a.chunks_per_wave, &nb));
+  // the nonzero walk gives each lane group its own chunks
+  const int32_t workers = (t.group_rows == 2 && a.rid) ? kWavesPerBlock * (kWave / t.lanes) : kWavesPerBlock;
+  SHIRO_TRY(grid_waves(plan, t, wl->W, workers, &a.chunks_per_wave, &nb));
   const int ntiles = (int)ceil_div(a.N, (int64_t)t.lanes * vec);
   a.xcd_remap = t.xcd_remap;
   dim3 grid(nb, ntiles);
@@ -1093,6 +1240,7 @@ int build_transposed(shiro_plan plan, hipStream_t s) {
   SHIRO_TRY(dev_alloc_n(&tr.ptr, U + 1));
   SHIRO_TRY(dev_alloc_n(&tr.row, nnz > 0 ? nnz : 1));
   SHIRO_TRY(dev_alloc_n(&tr.perm, nnz > 0 ? nnz : 1));
+  SHIRO_TRY(dev_alloc_n(&tr.rid, nnz > 0 ? nnz : 1));
   if (nnz == 0) {
     scan_generic(
         [] __device__(int64_t) -> int64_t { return 0; }, 0,
@@ -1100,13 +1248,13 @@ int build_transposed(shiro_plan plan, hipStream_t s) {
     tr.built = true;
     return SHIRO_OK;
   }
-  // scratch: iota values + sorted keys + sort scratch
-  const int64_t need = 2 * (nnz * 4 + 256) + sort_scratch_bytes(nnz);
+  // scratch: iota values + sort scratch; the sorted keys are the entries' rows
+  const int64_t need = (nnz * 4 + 256) + sort_scratch_bytes(nnz);
   SHIRO_TRY(ensure_scratch(plan, need));
   char* p = reinterpret_cast<char*>(plan->scratch);
   uint32_t* iota = reinterpret_cast<uint32_t*>(p);
-  uint32_t* skeys = reinterpret_cast<uint32_t*>(p + (nnz * 4 + 256) / 256 * 256);
-  void* sort_tmp = p + 2 * ((nnz * 4 + 256) / 256 * 256);
+  void* sort_tmp = p + (nnz * 4 + 256) / 256 * 256;
+  uint32_t* skeys = reinterpret_cast<uint32_t*>(tr.rid);
   k_iota<<<grid_for(nnz), kBlock, 0, s>>>(iota, nnz);
   SHIRO_LAUNCH_CHECK();
   int bits = 0;
@@ -1238,9 +1386,10 @@ namespace {
 int launch_pattern(shiro_plan plan, const shiro_tuning_t& t, const WorkList* wl, const int64_t* ptr,
                    const int32_t* idx, const float* vals, int64_t R, const void* X, int64_t ldx,
                    int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy, shiro_dtype out_dt,
-                   hipStream_t s, const int32_t* add_rows = nullptr) {
+                   hipStream_t s, const int32_t* add_rows = nullptr, const int32_t* rid = nullptr) {
   SpmmArgs a{};
   a.ptr = ptr;
+  a.rid = rid;
   a.idx = idx;
   a.vals = vals;
   a.X = X;
@@ -1309,6 +1458,7 @@ int build_rowbased(shiro_plan plan, hipStream_t s) {
   SHIRO_TRY(dev_alloc_n(&rb.ptr, R + 1));
   SHIRO_TRY(dev_alloc_n(&rb.col, std::max<int64_t>(nnz, 1)));
   SHIRO_TRY(dev_alloc_n(&rb.perm, std::max<int64_t>(nnz, 1)));
+  SHIRO_TRY(dev_alloc_n(&rb.rid, std::max<int64_t>(nnz, 1)));
   SHIRO_TRY(dev_alloc_n(&rb.agg_ptr, rows + 1));
   SHIRO_TRY(dev_alloc_n(&rb.agg_idx, std::max<int64_t>(R, 1)));
   SHIRO_TRY(dev_alloc_n(&rb.ones, std::max<int64_t>(R, 1)));
@@ -1327,7 +1477,8 @@ int build_rowbased(shiro_plan plan, hipStream_t s) {
   void* scan_tmp = scr + (std::max<int64_t>(R, 1) * 4 + 255) / 256 * 256;
   SHIRO_TRY(scan_generic(SegLen{sg.seg_begin, sg.seg_end}, R, OutPtr{rb.ptr}, rb.ptr + R, scan_tmp, s));
   if (nnz > 0 && R > 0) {
-    k_rb_fill<<<grid_for(nnz), kBlock, 0, s>>>(rb.ptr, R, sg.seg_begin, plan->col, nnz, rb.perm, rb.col);
+    k_rb_fill<<<grid_for(nnz), kBlock, 0, s>>>(rb.ptr, R, sg.seg_begin, plan->col, nnz, rb.perm, rb.col,
+                                                     rb.rid);
     SHIRO_LAUNCH_CHECK();
     if (plan->vmap) SHIRO_TRY(launch_compose(rb.perm, plan->vmap, nnz, s));
     k_rb_agg<<<grid_for(R), kBlock, 0, s>>>(sg.seg_csr, sg.seg_row, R, rb.agg_idx, row_csr, rb.ones);
@@ -1352,7 +1503,8 @@ int launch_partial_c(shiro_plan plan, const shiro_tuning_t& t, const float* vals
   // values in block-major order (they may change from call to call)
   k_gather_vals<<<grid_for(plan->nnz), kBlock, 0, s>>>(rb.perm, vals + plan->nz_begin, plan->nnz, rb.vals);
   SHIRO_LAUNCH_CHECK();
-  return launch_pattern(plan, t, wl, rb.ptr, rb.col, rb.vals, rb.R, B, ldb, N, in_dt, Cp, ldc, out_dt, s);
+  return launch_pattern(plan, t, wl, rb.ptr, rb.col, rb.vals, rb.R, B, ldb, N, in_dt, Cp, ldc, out_dt, s,
+                        nullptr, rb.rid);
 }
 
 int launch_aggregate_c(shiro_plan plan, const shiro_tuning_t& t, const void* Cp, int64_t ldc,
@@ -1391,6 +1543,7 @@ int launch_spmm_t(shiro_plan plan, const shiro_tuning_t& t, const float* vals, c
   SpmmArgs a{};
   a.ptr = plan->tr.ptr;
   a.idx = plan->tr.row;
+  a.rid = plan->tr.rid;
   a.vals = plan->tvals;
   a.X = dY;
   a.ldx = lddy;

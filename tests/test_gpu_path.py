@@ -301,6 +301,68 @@ def test_tunings_all_correct(shiro, run, knobs):
                          unroll=2, xcd_remap=0, wg_per_cu=8, group_rows=0)
 
 
+@pytest.mark.parametrize("knobs", [
+    dict(chunk=16, lanes=32, unroll=1),
+    dict(chunk=64, lanes=16, unroll=4, xcd_remap=1),
+    dict(chunk=512, lanes=8, unroll=2, wg_per_cu=2),
+    dict(chunk=128, lanes=64, unroll=4),
+    dict(chunk=2048, lanes=32, unroll=2, wg_per_cu=1),
+])
+def test_nonzero_walk_correct(shiro, run, knobs):
+    """The nonzero walk (group_rows 2) of the transposed product and of the
+    partial rows.  Small chunks cut rows into many carried pieces; with few
+    workers each lane group walks a long run of chunks (indices loaded one
+    step ahead across chunk ends)."""
+    dev = run.dev
+    kinds = (("spmm_t", torch.float32), ("spmm_t", torch.bfloat16), ("partial_c", torch.float32))
+    saved = {k: shiro.get_tuning(run.plan, k[0], run.N, k[1]) for k in kinds}
+    for k in kinds:
+        shiro.set_tuning(run.plan, k[0], run.N, k[1], group_rows=2, **knobs)
+    try:
+        Bp = shiro.pack_B(run.plan, run.B.to(dev))
+        dY = run.G.to(dev)
+        rdBp, rden, rdv, rdv_den = _bwd_refs(run, run.B.numpy(), run.G.numpy())
+        nz = slice(run.Ac.nz_begin, run.Ac.nz_begin + run.Ac.nnz_panel)
+        dBp = torch.empty(run.U, run.N, device=dev)
+        dvals = torch.zeros(run.A.nnz, device=dev)
+        shiro.spmm_backward(run.plan, run.Ad.vals, dY, Bp, dBpacked=dBp, dvals=dvals)
+        assert oracle.rel_err(dBp.cpu().numpy(), rdBp, rden) <= TOL_F32
+        assert oracle.rel_err(dvals.cpu().numpy()[nz], rdv, rdv_den) <= TOL_F32
+        # overwrite form: selected rows replaced, the others untouched
+        dB = torch.full((run.A.n_cols, run.N), 7.0, device=dev)
+        dv2 = torch.zeros_like(dvals)
+        shiro.spmm_backward(run.plan, run.Ad.vals, dY, Bp, dB=dB, dvals=dv2, dB_overwrite=True)
+        got = dB.cpu()
+        sel = torch.zeros(run.A.n_cols, dtype=torch.bool)
+        sel[torch.from_numpy(run.uc).long()] = True
+        assert torch.equal(got[sel], dBp.cpu())
+        assert bool((got[~sel] == 7.0).all())
+        assert torch.equal(dv2, dvals)
+        # add form on ones: each selected row is 1 + the same sum, rounded once
+        dBa = torch.ones(run.A.n_cols, run.N, device=dev)
+        shiro.spmm_backward(run.plan, run.Ad.vals, dY, Bp, dB=dBa)
+        assert torch.equal(dBa.cpu()[sel], (1.0 + dBp).cpu())
+        assert bool((dBa.cpu()[~sel] == 1.0).all())
+        # bfloat16 storage, float32 accumulation
+        Bph = shiro.pack_B(run.plan, run.B.to(torch.bfloat16).to(dev))
+        dBph = torch.empty(run.U, run.N, dtype=torch.bfloat16, device=dev)
+        dvh = torch.zeros_like(dvals)
+        shiro.spmm_backward(run.plan, run.Ad.vals, run.G.to(torch.bfloat16).to(dev), Bph, dBpacked=dBph, dvals=dvh)
+        assert oracle.rel_err(bf16_to_f32(dBph), rdBp, rden) <= TOL_BF16
+        assert oracle.rel_err(dvh.cpu().numpy()[nz], rdv, rdv_den) <= TOL_BF16
+        # the row-based scheme's partial rows
+        R, _ = shiro.select_c_rows(run.plan)
+        rs, off = oracle.select_c_rows(run.Ac)
+        Cp = shiro.partial_c(run.plan, run.Ad.vals, run.B.to(dev), R)
+        Bn = run.B.numpy()
+        ref = oracle.partial_c(run.Ac, Bn, rs, off)
+        den = oracle.partial_c(run.Ac, Bn, rs, off, abs_mode=True)
+        assert oracle.rel_err(Cp.cpu().numpy(), ref, den) <= TOL_F32
+    finally:
+        for k, t in saved.items():
+            shiro.set_tuning(run.plan, k[0], run.N, k[1], **t)
+
+
 def test_graph_replays_match_eager(shiro):
     """A captured select+pack+spmm+backward graph, replayed several times with
     eager work in between, gives bit-identical results to the eager calls."""
