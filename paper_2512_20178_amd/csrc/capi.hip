@@ -197,18 +197,19 @@ int ensure_tvals(shiro_plan plan, bool allocate) {
   return SHIRO_OK;
 }
 
-// Defaults from a sweep on MI355X (panel of a 2^24 R-MAT, N = 128): small
-// chunks, one nonzero in flight per lane group (high occupancy wins for
-// these gather-bound loops), 8 workgroups per CU.
+// Defaults from sweeps on MI355X (panel of a 2^24 R-MAT, N = 128): the
+// nonzero walk with four nonzeros in flight per lane group and chunks of 256
+// merge-path items for every kernel that has it; the sampled product keeps
+// its wavefront-per-row kernel with two in flight.
 shiro_tuning_t default_tuning(int kernel, int32_t, shiro_dtype) {
-  const bool row_based = kernel == SHIRO_KERNEL_PARTIAL_C || kernel == SHIRO_KERNEL_AGGREGATE_C;
+  const bool walk = kernel != SHIRO_KERNEL_SDDMM;
   shiro_tuning_t t;
-  t.chunk = 128;
+  t.chunk = walk ? 256 : 128;
   t.lanes = 64;
-  t.unroll = kernel == SHIRO_KERNEL_SPMM ? 1 : 2;
-  t.group_rows = row_based ? 1 : 0;  // the partial rows' segments are short
+  t.unroll = walk ? 4 : 2;
+  t.group_rows = walk ? 2 : 0;
   t.xcd_remap = 0;
-  t.wg_per_cu = (kernel == SHIRO_KERNEL_SPMM_T || row_based) ? 16 : 8;
+  t.wg_per_cu = walk ? 16 : 8;
   return t;
 }
 
@@ -221,9 +222,8 @@ int validate_tuning(int kernel, int32_t, shiro_dtype, const shiro_tuning_t& t) {
   if (t.unroll != 1 && t.unroll != 2 && t.unroll != 4)
     return set_error(SHIRO_ERR_INVALID_ARG, "tuning: unroll must be 1, 2 or 4");
   if (t.group_rows < 0 || t.group_rows > 2) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: group_rows must be 0, 1 or 2");
-  if (t.group_rows == 2 && kernel != SHIRO_KERNEL_SPMM_T && kernel != SHIRO_KERNEL_PARTIAL_C)
-    return set_error(SHIRO_ERR_INVALID_ARG,
-                     "tuning: group_rows 2 (nonzero walk) needs rows without gaps: transposed product or partial rows only");
+  if (t.group_rows == 2 && kernel == SHIRO_KERNEL_SDDMM)
+    return set_error(SHIRO_ERR_INVALID_ARG, "tuning: the sampled product has no nonzero walk (group_rows 0 or 1)");
   if (t.xcd_remap != 0 && t.xcd_remap != 1) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: xcd_remap must be 0 or 1");
   if (t.wg_per_cu < 1 || t.wg_per_cu > 32) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: wg_per_cu outside [1, 32]");
   return SHIRO_OK;
@@ -277,6 +277,8 @@ static void plan_free(shiro_plan plan) {
   dev_free(plan->rb.col);
   dev_free(plan->rb.perm);
   dev_free(plan->rb.rid);
+  dev_free(plan->rb.agg_rid);
+  dev_free(plan->row_rid);
   dev_free(plan->rb.agg_ptr);
   dev_free(plan->rb.agg_idx);
   dev_free(plan->rb.ones);
@@ -423,7 +425,7 @@ static int tune_one(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt, Tune
     }
   // stage 2: lane width, occupancy, XCD placement around the best
   const shiro_tuning_t base = best;
-  const bool walk = kernel == SHIRO_KERNEL_SPMM_T || kernel == SHIRO_KERNEL_PARTIAL_C;
+  const bool walk = kernel != SHIRO_KERNEL_SDDMM;
   for (int grp = 0; grp <= (walk ? 2 : 1); ++grp)
     for (int lanes : {64, 32, 16})
       for (int wg : {4, 8, 16})
@@ -829,6 +831,7 @@ SHIRO_API int shiro_prepare(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t
     const shiro_tuning_t t = tuning_for(plan, SHIRO_KERNEL_SPMM, N, dt);
     SHIRO_TRY(ensure_rows_work(plan, t.chunk, true, s, &wl));
     SHIRO_TRY(ensure_carry(plan, (int64_t)wl->W * 2 * N, true));
+    SHIRO_TRY(ensure_row_rid(plan, true, s));
   }
   if (ops & SHIRO_OP_BACKWARD) {
     SHIRO_TRY(build_transposed(plan, s));

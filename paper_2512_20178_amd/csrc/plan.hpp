@@ -61,6 +61,7 @@ struct RowBased {
   int32_t* perm = nullptr;      // nnz: CSR position of each nonzero, block-major
   int32_t* rid = nullptr;       // nnz: entry of each nonzero, block-major
   int64_t* agg_ptr = nullptr;   // rows + 1: each panel row's entries
+  int32_t* agg_rid = nullptr;   // R: panel row of each entry of the sum pattern
   int32_t* agg_idx = nullptr;   // R: entry position of each (row, block) pair, blocks ascending
   float* ones = nullptr;        // R: unit weights of the sum
   int32_t* iota = nullptr;      // rows: identity row map (sum added into Y)
@@ -103,6 +104,7 @@ struct shiro_plan_s {
   int32_t* unique_cols = nullptr;  // capacity min(nnz, n_cols)
   int64_t* block_off = nullptr;    // P + 1
   int32_t* colmap = nullptr;       // nnz
+  int32_t* row_rid = nullptr;      // nnz: row of each nonzero (for the nonzero walk)
   std::vector<int64_t> h_block_off;
 
   // derived structures
@@ -182,6 +184,8 @@ int build_worklist(const int64_t* ptr, int64_t R, int64_t nnz, int32_t chunk, Wo
 int build_transposed(shiro_plan plan, hipStream_t s);
 int build_segments(shiro_plan plan, hipStream_t s);
 int build_rowbased(shiro_plan plan, hipStream_t s);
+// The panel rows' ids per nonzero (plan->row_rid), built once.
+int ensure_row_rid(shiro_plan plan, bool allocate, hipStream_t s);
 // Joint row-column strategy (host): minimum weighted vertex cover of one
 // bipartite graph, and the per-panel plan over its off-diagonal blocks.
 int solve_mvc(int64_t n_left, int64_t n_right, int64_t n_edges, const int32_t* left,

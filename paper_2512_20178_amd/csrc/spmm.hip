@@ -449,23 +449,23 @@ __global__ __launch_bounds__(kBlock) void k_spmm_grp(SHIRO_SPMM_PARAMS(TIN, TOUT
   }
 }
 
-// Variant for patterns whose rows are all non-empty and mostly hold one or
-// two nonzeros (the transposed pattern, one row per selected column; the
-// row-based scheme's partial rows).  Lane group g of a wavefront owns whole
-// chunks and walks their nonzeros UNROLL at a time without regard to row
-// boundaries, so it keeps UNROLL dense rows in flight even where every row
-// holds a single nonzero.  rid[k] is the row of nonzero k; a row's sum is
-// written when the walk reaches a nonzero of another row or the chunk's end.
-// Rows cut by the chunk's ends go to its carry slots as in k_spmm: the first
-// row's piece (empty or not) when that row began in an earlier chunk, the
-// last row's piece when the chunk holds any of it.  A group's chunks are
-// consecutive, so its nonzeros form one contiguous run and each step's
-// indices are loaded one step ahead, across chunk ends too.  Sums inside a
-// row keep pattern order, so results stay reproducible.  Rows written once
-// (the output, the overwritten dB rows) and the dense rows D read once are
-// marked non-temporal, so they do not push the gathered rows out of the
-// caches (on the 2^24 R-MAT panel this took the transposed product without
-// dvals from 469 to 344 us).
+// Nonzero walk.  Lane group g of a wavefront owns whole chunks and walks
+// their nonzeros UNROLL at a time without regard to row boundaries, so it
+// keeps UNROLL dense rows in flight whatever the row lengths (wave-per-row
+// and group-per-row kernels stall once per row, and the short rows of
+// power-law patterns dominate).  rid[k] is the row of nonzero k; a row's
+// sum is written when the walk reaches a nonzero of another row or the
+// chunk's end, and rows the walk steps over (no nonzeros) are written as
+// zeros.  Rows cut by the chunk's ends go to its carry slots as in k_spmm:
+// the first row's piece (empty or not) when that row began in an earlier
+// chunk, the last row's piece when the chunk holds any of it.  A group's
+// chunks are consecutive, so its nonzeros form one contiguous run and each
+// step's indices are loaded one step ahead, across chunk ends too.  Sums
+// inside a row keep pattern order, so results stay reproducible.  Rows
+// written once (the output, overwritten dB rows) and the dense rows D read
+// once are marked non-temporal, so they do not push the gathered rows out
+// of the caches (on the 2^24 R-MAT panel this took the transposed product
+// without dvals from 469 to 344 us).
 template <typename TIN, typename TOUT, int LANES, int VEC, int UNROLL, bool DOT, int SCAT>
 __global__ __launch_bounds__(kBlock) void k_spmm_flat(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
   constexpr int G = kWave / LANES;
@@ -498,6 +498,10 @@ __global__ __launch_bounds__(kBlock) void k_spmm_flat(SHIRO_SPMM_PARAMS(TIN, TOU
     const int64_t j0 = chunk_nz[w], j1 = chunk_nz[w + 1];
     if (i0 >= R) break;
     const bool has_head = j0 > ptr[i0];
+    // rows below row_end whose ends fall in this chunk are complete; `next`
+    // is the first of them not written yet
+    const int32_t row_end = i1 < R ? i1 : R;
+    int32_t next = has_head ? i0 + 1 : i0;
     float* const head_slot = carry + (w * 2) * N + c;
     float* const tail_slot = carry + (w * 2 + 1) * N + c;
     if (has_head && ptr[i0 + 1] <= j0 && cvalid) {  // row i0 holds nothing here
@@ -506,28 +510,40 @@ __global__ __launch_bounds__(kBlock) void k_spmm_flat(SHIRO_SPMM_PARAMS(TIN, TOU
       for (int e = 0; e < VEC; ++e) z[e] = 0.f;
       Elem<float>::template store<VEC>(head_slot, z);
     }
+    // a complete row's sum: into the output, and into (or onto) its dB row
+    auto put = [&](int32_t r, int32_t sidx, const float(&a)[VEC], bool zero) {
+      if (out) Elem<TOUT>::template store_nt<VEC>(out + (int64_t)r * ldo + c, a);
+      if constexpr (SCAT == 1) {
+        if (!zero) {
+          float pre[VEC];
+          Elem<TOUT>::template load<VEC>(scat + (int64_t)sidx * lds + c, pre);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) pre[e] += a[e];
+          Elem<TOUT>::template store<VEC>(scat + (int64_t)sidx * lds + c, pre);
+        }
+      } else if constexpr (SCAT == 2) {
+        Elem<TOUT>::template store_nt<VEC>(scat + (int64_t)sidx * lds + c, a);
+      }
+    };
+    // complete rows [next, lim) hold no nonzeros
+    auto zero_rows = [&](int32_t lim) {
+      for (; next < lim; ++next) {
+        if (!cvalid) continue;
+        float z[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) z[e] = 0.f;
+        put(next, SCAT ? scat_idx[next] : 0, z, true);
+      }
+    };
     int32_t cur = -1, scur = 0;  // open row and its scatter row
     float acc[VEC];
 #pragma unroll
     for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
     auto flush = [&]() {
       if (!cvalid) return;
-      if (cur == i0 && has_head) {
-        Elem<float>::template store<VEC>(head_slot, acc);
-      } else if (cur == i1) {
-        Elem<float>::template store<VEC>(tail_slot, acc);
-      } else {
-        if (out) Elem<TOUT>::template store_nt<VEC>(out + (int64_t)cur * ldo + c, acc);
-        if constexpr (SCAT == 1) {
-          float pre[VEC];
-          Elem<TOUT>::template load<VEC>(scat + (int64_t)scur * lds + c, pre);
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) pre[e] += acc[e];
-          Elem<TOUT>::template store<VEC>(scat + (int64_t)scur * lds + c, pre);
-        } else if constexpr (SCAT == 2) {
-          Elem<TOUT>::template store_nt<VEC>(scat + (int64_t)scur * lds + c, acc);
-        }
-      }
+      if (cur == i0 && has_head) Elem<float>::template store<VEC>(head_slot, acc);
+      else if (cur == i1) Elem<float>::template store<VEC>(tail_slot, acc);
+      else put(cur, scur, acc, false);
     };
     for (int64_t k = j0; k < j1; k += UNROLL) {
       bool ok[UNROLL];
@@ -561,8 +577,10 @@ __global__ __launch_bounds__(kBlock) void k_spmm_flat(SHIRO_SPMM_PARAMS(TIN, TOU
       for (int u = 0; u < UNROLL; ++u) {
         if (ok[u] && ri[u] != cur) {
           if (cur >= 0) flush();
+          zero_rows(ri[u]);
           cur = ri[u];
           scur = sc[u];
+          if (next <= cur) next = cur + 1;
 #pragma unroll
           for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
         }
@@ -587,6 +605,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_flat(SHIRO_SPMM_PARAMS(TIN, TOU
       }
     }
     if (cur >= 0) flush();
+    zero_rows(row_end);
   }
 }
 
@@ -895,6 +914,12 @@ __global__ void k_transpose_finish(const uint32_t* __restrict__ skeys,
     if (j == 0 || skeys[j] != skeys[j - 1]) tptr[skeys[j]] = j;
     if (j == nnz - 1) tptr[U] = nnz;
   }
+}
+
+// rid[k] = the row holding entry k of a CSR pattern (binary search).
+__global__ void k_row_ids(const int64_t* __restrict__ ptr, int64_t rows, int64_t n, int32_t* __restrict__ rid) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    rid[k] = (int32_t)row_of(ptr, rows, k);
 }
 
 // Segment starts: first nonzero of a row, or a change of column block.
@@ -1434,17 +1459,29 @@ static const float* plan_values(shiro_plan plan, const float* vals, hipStream_t 
   return plan->svals;
 }
 
+int ensure_row_rid(shiro_plan plan, bool allocate, hipStream_t s) {
+  if (plan->row_rid) return SHIRO_OK;
+  if (!allocate) return set_error(SHIRO_ERR_CAPTURING, "spmm: row ids for the nonzero walk not prepared before capture");
+  SHIRO_TRY(dev_alloc_n(&plan->row_rid, std::max<int64_t>(plan->nnz, 1)));
+  if (plan->nnz > 0) {
+    k_row_ids<<<grid_for(plan->nnz), kBlock, 0, s>>>(plan->row_ptr, plan->rows, plan->nnz, plan->row_rid);
+    SHIRO_LAUNCH_CHECK();
+  }
+  return SHIRO_OK;
+}
+
 int launch_spmm(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* X,
                 int64_t ldx, int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy,
                 shiro_dtype out_dt, hipStream_t s) {
   if (plan->rows == 0 || N == 0) return SHIRO_OK;
   const WorkList* wl;
   SHIRO_TRY(ensure_rows_work(plan, t.chunk, !stream_capturing(s), s, &wl));
+  if (t.group_rows == 2) SHIRO_TRY(ensure_row_rid(plan, !stream_capturing(s), s));
   SHIRO_TRY(ensure_carry(plan, (int64_t)wl->W * 2 * N, !stream_capturing(s)));
   const float* v = plan_values(plan, vals, s);
   SHIRO_LAUNCH_CHECK();
   return launch_pattern(plan, t, wl, plan->row_ptr, plan->colmap, v, plan->rows, X, ldx, N, in_dt, Y, ldy,
-                        out_dt, s);
+                        out_dt, s, nullptr, t.group_rows == 2 ? plan->row_rid : nullptr);
 }
 
 int build_rowbased(shiro_plan plan, hipStream_t s) {
@@ -1460,6 +1497,7 @@ int build_rowbased(shiro_plan plan, hipStream_t s) {
   SHIRO_TRY(dev_alloc_n(&rb.perm, std::max<int64_t>(nnz, 1)));
   SHIRO_TRY(dev_alloc_n(&rb.rid, std::max<int64_t>(nnz, 1)));
   SHIRO_TRY(dev_alloc_n(&rb.agg_ptr, rows + 1));
+  SHIRO_TRY(dev_alloc_n(&rb.agg_rid, std::max<int64_t>(R, 1)));
   SHIRO_TRY(dev_alloc_n(&rb.agg_idx, std::max<int64_t>(R, 1)));
   SHIRO_TRY(dev_alloc_n(&rb.ones, std::max<int64_t>(R, 1)));
   SHIRO_TRY(dev_alloc_n(&rb.vals, std::max<int64_t>(nnz, 1)));
@@ -1486,6 +1524,10 @@ int build_rowbased(shiro_plan plan, hipStream_t s) {
   }
   k_rb_agg_ptr<<<grid_for(rows + 1), kBlock, 0, s>>>(row_csr, R, rows, rb.agg_ptr);
   SHIRO_LAUNCH_CHECK();
+  if (R > 0) {
+    k_row_ids<<<grid_for(R), kBlock, 0, s>>>(rb.agg_ptr, rows, R, rb.agg_rid);
+    SHIRO_LAUNCH_CHECK();
+  }
   SHIRO_HIP(hipStreamSynchronize(s));
   rb.built = true;
   return SHIRO_OK;
@@ -1517,7 +1559,7 @@ int launch_aggregate_c(shiro_plan plan, const shiro_tuning_t& t, const void* Cp,
   SHIRO_TRY(ensure_rb_work(plan, 1, t.chunk, !cap, s, &wa));
   SHIRO_TRY(ensure_carry(plan, (int64_t)wa->W * 2 * N, !cap));
   return launch_pattern(plan, t, wa, rb.agg_ptr, rb.agg_idx, rb.ones, plan->rows, Cp, ldc, N, in_dt, Y, ldy,
-                        out_dt, s, accumulate ? rb.iota : nullptr);
+                        out_dt, s, accumulate ? rb.iota : nullptr, rb.agg_rid);
 }
 
 int launch_spmm_t(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* dY,

@@ -309,17 +309,29 @@ def test_tunings_all_correct(shiro, run, knobs):
     dict(chunk=2048, lanes=32, unroll=2, wg_per_cu=1),
 ])
 def test_nonzero_walk_correct(shiro, run, knobs):
-    """The nonzero walk (group_rows 2) of the transposed product and of the
-    partial rows.  Small chunks cut rows into many carried pieces; with few
-    workers each lane group walks a long run of chunks (indices loaded one
-    step ahead across chunk ends)."""
+    """The nonzero walk (group_rows 2) of every kernel that has it: forward,
+    transposed product, partial rows and their sum.  Small chunks cut rows
+    into many carried pieces; with few workers each lane group walks a long
+    run of chunks (indices loaded one step ahead across chunk ends); rows
+    with no nonzeros (the hub, empty and R-MAT cases) are written as zeros,
+    or left alone when the sum is added."""
     dev = run.dev
-    kinds = (("spmm_t", torch.float32), ("spmm_t", torch.bfloat16), ("partial_c", torch.float32))
+    kinds = (("spmm", torch.float32), ("spmm", torch.bfloat16), ("spmm_t", torch.float32),
+             ("spmm_t", torch.bfloat16), ("partial_c", torch.float32), ("aggregate_c", torch.float32))
     saved = {k: shiro.get_tuning(run.plan, k[0], run.N, k[1]) for k in kinds}
     for k in kinds:
         shiro.set_tuning(run.plan, k[0], run.N, k[1], group_rows=2, **knobs)
     try:
         Bp = shiro.pack_B(run.plan, run.B.to(dev))
+        Yref, Yden = _fwd_ref(run, run.B.numpy())
+        # forward on a buffer of NaNs: every row, empty ones included, is written
+        Y = torch.full((run.Ac.M, run.N), float("nan"), device=dev)
+        shiro.spmm(run.plan, run.Ad.vals, Bp, out=Y)
+        assert oracle.rel_err(Y.cpu().numpy(), Yref, Yden) <= TOL_F32
+        Bph0 = shiro.pack_B(run.plan, run.B.to(torch.bfloat16).to(dev))
+        for odt in (torch.bfloat16, torch.float32):
+            Yh = shiro.spmm(run.plan, run.Ad.vals, Bph0, out_dtype=odt)
+            assert oracle.rel_err(bf16_to_f32(Yh), Yref, Yden) <= TOL_BF16
         dY = run.G.to(dev)
         rdBp, rden, rdv, rdv_den = _bwd_refs(run, run.B.numpy(), run.G.numpy())
         nz = slice(run.Ac.nz_begin, run.Ac.nz_begin + run.Ac.nnz_panel)
@@ -358,6 +370,13 @@ def test_nonzero_walk_correct(shiro, run, knobs):
         ref = oracle.partial_c(run.Ac, Bn, rs, off)
         den = oracle.partial_c(run.Ac, Bn, rs, off, abs_mode=True)
         assert oracle.rel_err(Cp.cpu().numpy(), ref, den) <= TOL_F32
+        # their sum, written over NaNs and added onto ones
+        Yr = torch.full((run.Ac.M, run.N), float("nan"), device=dev)
+        shiro.aggregate_c(run.plan, Cp, out=Yr)
+        assert oracle.rel_err(Yr.cpu().numpy(), Yref, Yden) <= TOL_F32
+        Ya = torch.ones(run.Ac.M, run.N, device=dev)
+        shiro.aggregate_c(run.plan, Cp, out=Ya, accumulate=True)
+        assert torch.equal(Ya, 1.0 + Yr)
     finally:
         for k, t in saved.items():
             shiro.set_tuning(run.plan, k[0], run.N, k[1], **t)
