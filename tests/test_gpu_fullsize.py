@@ -156,6 +156,33 @@ def test_rmat24_spmm_and_backward_sampled(shiro, rmat24):
     del dB
 
 
+def test_rmat24_walk_matches_row_kernels(shiro, rmat24):
+    """At full size, the nonzero walk and the group-rows kernel sum every row
+    in the same order on the same merge-path chunks, so forward, dB rows and
+    fused dvals agree bit for bit; with the oracle-checked kernels above this
+    ties the walk to the oracle on all 131072 rows and 4.15M values."""
+    plan, B, N, A = rmat24["plan"], rmat24["B"], rmat24["N"], rmat24["A"]
+    dev = B.device
+    saved = {k: shiro.get_tuning(plan, k, N) for k in ("spmm", "spmm_t")}
+    G = synth.dense(plan.info()["rows"], N, 0, synth.STREAM_DY, device=dev)
+    Bp = shiro.pack_B(plan, B)
+    outs = []
+    try:
+        for grp in (1, 2):
+            for k in ("spmm", "spmm_t"):
+                shiro.set_tuning(plan, k, N, chunk=256, lanes=32, unroll=4, group_rows=grp, xcd_remap=0, wg_per_cu=16)
+            Y = shiro.spmm(plan, A.vals, Bp)
+            dB = torch.zeros(A.n_cols, N, device=dev)
+            dv = torch.zeros(A.nnz, device=dev)
+            shiro.spmm_backward(plan, A.vals, G, Bp, dB=dB, dvals=dv, dB_overwrite=True)
+            outs.append((Y, dB, dv))
+    finally:
+        for k, t in saved.items():
+            shiro.set_tuning(plan, k, N, **t)
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+
+
 def test_rmat24_row_based_and_joint_sampled(shiro, rmat24):
     """The row-based scheme and the joint strategy at full size, as the
     benchmark runs them: Rows per block bit-exact against the oracle, the
