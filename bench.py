@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+FP32_VECTOR_PEAK_GFLOPS = 157300.0  # MI355X FP32 vector, published (no MFMA on this path)
 
 
 def log(*a):
@@ -246,6 +247,9 @@ def main():
                    "U": U, "N": N, "step": "select+pack_B+spmm+spmm_backward(dB rows, dvals)"},
         "roofline": roofline,
         "step_hbm_frac": round(alg_step / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        # the flop side of the roofline: the whole step's 2*nnz*N per product
+        # against the FP32 vector peak (the large workloads reach 5-12 flop/B)
+        "step_fp32_vector_frac": round(gflops / FP32_VECTOR_PEAK_GFLOPS, 4),
         "step_us_stats": {"mean": round(ms_step * 1e3, 2), "median": round(float(np.median(per_step)) * 1e3, 2),
                           "min": round(float(np.min(per_step)) * 1e3, 2)},
         "kernels_us": {k: round(v, 2) for k, v in kern_us.items()},
