@@ -224,8 +224,12 @@ def main():
         # counters taken on another build of these kernels or another tuning are stale
         if pmc.get("src_hash") == src_hash("csrc/spmm.hip", "csrc/common.hpp", "csrc/capi.hip", "tuning_mi355x.txt"):
             traffic = pmc.get("hbm_bytes_per_launch")
-    kernels_of = {"pack_B": "k_pack", "spmm": "k_spmm + k_fixup",
-                  "backward": "k_gather_vals + k_spmm<dot> + k_fixup + k_scatter_vals"}
+    # the product kernel each op ran, from the plan's tuning (group_rows)
+    kname = {0: "k_spmm", 1: "k_spmm_grp", 2: "k_spmm_flat"}
+    kf = kname[shiro.get_tuning(plan, "spmm", N, tdt)["group_rows"]]
+    kb = kname[shiro.get_tuning(plan, "spmm_t", N, tdt)["group_rows"]]
+    kernels_of = {"pack_B": "k_pack", "spmm": f"{kf} + k_fixup",
+                  "backward": f"k_gather_vals + {kb}<dot> + k_fixup + k_scatter_vals"}
     roofline = {"bound": "hbm", "kernel": f"{dom} ({kernels_of[dom]})", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes": int(alg[dom]), "duration_us": round(kern_us[dom], 2)}
