@@ -1369,7 +1369,10 @@ int launch_pack(shiro_plan plan, const void* B, int64_t ldb, int32_t N, shiro_dt
                 int64_t ldp, hipStream_t s) {
   const int64_t U = plan->U;
   if (U == 0 || N == 0) return SHIRO_OK;
-  const unsigned nb = grid_for(U * 8, (int64_t)plan->num_cus * 8);
+  // Four workgroups per CU: on the 2^24 R-MAT panel (FP32, N = 128) 2, 4, 8
+  // and 16 gave 315, 246, 261 and 270 us -- fewer random rows of the large B
+  // in flight at once run faster, down to the point where latency shows.
+  const unsigned nb = grid_for(U * 8, (int64_t)plan->num_cus * 4);
   if (dt == SHIRO_F32) {
     const int v = vec_for<float>(N, {{B, ldb}, {Bp, ldp}});
     const int64_t lanes = effective_lanes(64, N, v);
