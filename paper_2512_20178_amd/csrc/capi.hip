@@ -428,7 +428,7 @@ static int tune_one(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt, Tune
   const bool walk = kernel != SHIRO_KERNEL_SDDMM;
   for (int grp = 0; grp <= (walk ? 2 : 1); ++grp)
     for (int lanes : {64, 32, 16})
-      for (int wg : {4, 8, 16})
+      for (int wg : {2, 4, 8, 16})
         for (int xcd : {0, 1}) {
           shiro_tuning_t t = base;
           t.group_rows = grp;
