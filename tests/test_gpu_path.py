@@ -382,6 +382,30 @@ def test_nonzero_walk_correct(shiro, run, knobs):
             shiro.set_tuning(run.plan, k[0], run.N, k[1], **t)
 
 
+def test_allocator_failure_reports_oom(shiro):
+    """An allocator callback that hands out no memory makes plan construction
+    fail with SHIRO_ERR_OOM and a message (no launch touches a null buffer),
+    and the library works again once hipMalloc is restored."""
+    from paper_2512_20178_amd import _lib
+
+    A, N = make_case("rmat12_P8_p0")
+    Ad = A.to(torch.device("cuda"))
+    alloc = _lib.ALLOC_FN(lambda n, c: None)
+    free = _lib.FREE_FN(lambda p, n, c: None)
+    assert shiro._L().shiro_set_allocator(alloc, free, None) == 0
+    try:
+        with pytest.raises(_lib.ShiroError) as e:
+            plan = shiro.partition(Ad.row_ptr, Ad.col, A.n_rows, A.n_cols, A.P, A.p)
+            shiro.select_rows(plan)
+        assert e.value.name == "OOM"
+        assert "allocator returned NULL" in str(e.value)
+    finally:
+        shiro.use_torch_allocator(False)
+    plan = shiro.partition(Ad.row_ptr, Ad.col, A.n_rows, A.n_cols, A.P, A.p)
+    U, _ = shiro.select_rows(plan)
+    assert U == len(oracle.select(oracle.Csr.from_synth(A))[0])
+
+
 def test_graph_replays_match_eager(shiro):
     """A captured select+pack+spmm+backward graph, replayed several times with
     eager work in between, gives bit-identical results to the eager calls."""
