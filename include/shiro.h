@@ -346,9 +346,11 @@ SHIRO_API int shiro_joint_plan(shiro_plan plan, const int64_t* h_w_row, const in
                                uint8_t* h_assign, int64_t* h_stats, int32_t n_threads,
                                shiro_stream_t stream);
 
-/* Build everything the per-call steps need for (N, dtype, ops) - work lists,
- * transposed pattern, row-based structures, carry buffers - so later calls
- * neither allocate nor synchronise (required before graph capture).  Ops
+/* Build everything the per-call steps need for (N, dtype, ops) - work lists
+ * for the tuning in force, transposed pattern, per-nonzero row ids of the
+ * nonzero walk, row-based structures, carry buffers - so later calls
+ * neither allocate nor synchronise (required before graph capture; a tuning
+ * set afterwards with another chunk needs another prepare).  Ops
  * other than SHIRO_OP_ROW_BASED need shiro_select_rows first (NOT_READY).
  * Synchronises the stream. */
 SHIRO_API int shiro_prepare(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t ops,
