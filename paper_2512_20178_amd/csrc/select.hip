@@ -149,20 +149,39 @@ struct PopcountIn {
 
 // Down pass of the selection scan.  A workgroup owns kSelItems*256 words:
 // it scans their popcounts (plus the tile offset from the tile scan), writes
-// each word's packed offset into the word table, and then compacts the
-// ids of the set bits one id per lane — lane t of the workgroup takes ids
-// t, t+256, ... of the tile, so stores of neighbouring ids are neighbours
-// and no lane walks a dense word alone.
+// each word's packed offset into the word table, and then compacts the ids
+// of the set bits, so that stores of neighbouring ids are neighbours and no
+// lane walks a dense word alone.  A sparse tile (most of them: 7% of the
+// bits are set on the 2^24 R-MAT panel) is compacted output by output: lane
+// t takes outputs t, t+256, ..., finds the word holding each by binary
+// search over the tile's word offsets in LDS and the bit inside it by
+// popcount halving.  A dense tile is scanned bit by bit, one id per lane.
 constexpr int kSelItems = 4;
+
+// Position of the r-th set bit (r counted from 0) of w; r < popcount(w).
+__device__ __forceinline__ uint32_t select_bit(uint32_t w, uint32_t r) {
+  uint32_t pos = 0;
+#pragma unroll
+  for (int h = 16; h >= 1; h >>= 1) {
+    const uint32_t c = __popc(w & ((1u << h) - 1u));
+    const bool up = r >= c;
+    r = up ? r - c : r;
+    w = up ? w >> h : w;
+    pos += up ? (uint32_t)h : 0u;
+  }
+  return pos;
+}
 
 __global__ __launch_bounds__(kBlock) void k_select_down(uint32_t* __restrict__ wtab, int64_t n_words,
                                                         const int64_t* __restrict__ tile_off,
                                                         int32_t* __restrict__ unique_cols) {
+  constexpr int TW = kBlock * kSelItems;  // words per tile
   __shared__ int64_t lds[kWavesPerBlock];
-  __shared__ uint32_t sbits[kBlock * kSelItems];
-  __shared__ uint32_t spref[kBlock * kSelItems];
-  const int64_t tile0 = (int64_t)blockIdx.x * (kBlock * kSelItems);
+  __shared__ uint32_t sbits[TW];
+  __shared__ uint32_t spref[TW];  // offset of each word inside the tile
+  const int64_t tile0 = (int64_t)blockIdx.x * TW;
   const int64_t base = tile0 + (int64_t)threadIdx.x * kSelItems;
+  const int64_t toff = tile_off[blockIdx.x];
   uint32_t bits[kSelItems];
   int64_t s = 0;
 #pragma unroll
@@ -170,21 +189,34 @@ __global__ __launch_bounds__(kBlock) void k_select_down(uint32_t* __restrict__ w
     bits[i] = (base + i < n_words) ? wtab[2 * (base + i)] : 0u;
     s += __popc(bits[i]);
   }
-  int64_t ex = block_exclusive_scan<int64_t>(s, lds, nullptr) + tile_off[blockIdx.x];
+  int64_t tot;
+  int64_t ex = block_exclusive_scan<int64_t>(s, lds, &tot);
 #pragma unroll
   for (int i = 0; i < kSelItems; ++i) {
-    if (base + i < n_words) wtab[2 * (base + i) + 1] = (uint32_t)ex;
+    if (base + i < n_words) wtab[2 * (base + i) + 1] = (uint32_t)(toff + ex);
     sbits[threadIdx.x * kSelItems + i] = bits[i];
     spref[threadIdx.x * kSelItems + i] = (uint32_t)ex;
     ex += __popc(bits[i]);
   }
   __syncthreads();
-  const int32_t ids = kBlock * kSelItems * 32;
-  for (int32_t j = threadIdx.x; j < ids; j += kBlock) {
-    const int32_t lw = j >> 5;
-    const uint32_t b = (uint32_t)j & 31u;
-    const uint32_t wb = sbits[lw];
-    if ((wb >> b) & 1u) unique_cols[spref[lw] + __popc(wb & ((1u << b) - 1u))] = (int32_t)((tile0 << 5) + j);
+  const int32_t count = (int32_t)tot;
+  if (count <= TW * 4) {  // sparse: walk the outputs
+    for (int32_t o = threadIdx.x; o < count; o += kBlock) {
+      int32_t lo = 0, hi = TW - 1;  // last word whose offset is <= o
+      while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if ((int32_t)spref[mid] <= o) lo = mid; else hi = mid - 1;
+      }
+      const uint32_t b = select_bit(sbits[lo], (uint32_t)(o - (int32_t)spref[lo]));
+      unique_cols[toff + o] = (int32_t)(((tile0 + lo) << 5) + b);
+    }
+  } else {  // dense: walk the bits
+    for (int32_t j = threadIdx.x; j < TW * 32; j += kBlock) {
+      const int32_t lw = j >> 5;
+      const uint32_t b = (uint32_t)j & 31u;
+      const uint32_t wb = sbits[lw];
+      if ((wb >> b) & 1u) unique_cols[toff + spref[lw] + __popc(wb & ((1u << b) - 1u))] = (int32_t)((tile0 << 5) + j);
+    }
   }
 }
 
