@@ -762,3 +762,9 @@ def test_error_paths_on_device(shiro):
     with pytest.raises(shiro.ShiroError) as e:
         shiro.set_tuning(plan, "spmm", 4, lanes=12)
     assert e.value.name == "INVALID_ARG"
+    with pytest.raises(shiro.ShiroError) as e:  # the sampled product has no nonzero walk
+        shiro.set_tuning(plan, "sddmm", 4, group_rows=2)
+    assert e.value.name == "INVALID_ARG"
+    with pytest.raises(shiro.ShiroError) as e:
+        shiro.set_tuning(plan, "spmm_t", 4, group_rows=3)
+    assert e.value.name == "INVALID_ARG"
