@@ -239,17 +239,13 @@ struct Elem<bf16_t> {
   }
 };
 
-// Raw 16-byte (or narrower) copy of VEC elements of T, bit-exact.  The
-// 16-byte form streams both ways (non-temporal load and store): on the
-// 2^24 R-MAT panel the FP32 pack went from 246 to 236 us with the store
-// marked too, and the SpMM that reads the packed rows next did not slow.
+// Raw 16-byte (or narrower) copy of VEC elements of T, bit-exact.
 template <typename T, int VEC>
 struct RawVec {
   static constexpr int kBytes = VEC * (int)sizeof(T);
   __device__ __forceinline__ static void copy(const T* __restrict__ src, T* __restrict__ dst) {
     if constexpr (kBytes == 16) {
-      __builtin_nontemporal_store(__builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src)),
-                                  reinterpret_cast<u32x4*>(dst));
+      *reinterpret_cast<u32x4*>(dst) = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src));
     } else if constexpr (kBytes == 8) {
       *reinterpret_cast<u32x2*>(dst) = *reinterpret_cast<const u32x2*>(src);
     } else {
