@@ -80,7 +80,7 @@ def src_hash(*names):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: the per-rank path has no collectives; "
+        print(json.dumps({"error": "the benchmark runs on one GPU: the per-rank path has no collectives; "
                                    "run with --gpus 1"}))
         sys.exit(2)
 
