@@ -105,3 +105,59 @@ def test_random_shapes(shiro, seed):
         js = shiro.JointSpMM(Ad.row_ptr, Ad.col, A.n_rows, A.n_cols, A.P, A.p)
         Yj = js.forward(Ad.vals, Bd)
         assert oracle.rel_err(Yj.float().cpu().numpy(), Yref, den) <= tol
+
+
+def random_tuning(rng, walk=True):
+    return dict(chunk=int(rng.choice([16, 48, 100, 128, 512, 2048])),
+                lanes=int(rng.choice([8, 16, 32, 64])),
+                unroll=int(rng.choice([1, 2, 4])),
+                group_rows=int(rng.integers(0, 3 if walk else 2)),
+                xcd_remap=int(rng.integers(0, 2)),
+                wg_per_cu=int(rng.choice([1, 2, 4, 8, 16])))
+
+
+@pytest.mark.parametrize("seed", range(10, 22))
+def test_random_shapes_random_tunings(shiro, seed):
+    """Random shapes with a random launch configuration per kernel family
+    (chunk sizes that are not powers of two, every lane width, depth and
+    layout, XCD remap, one to sixteen workgroups per CU)."""
+    A, N, rng = random_case(seed)
+    dtype = torch.float32 if seed % 2 == 0 else torch.bfloat16
+    tol = TOL_F32 if dtype == torch.float32 else TOL_BF16
+    dev = torch.device("cuda")
+    Ad = A.to(dev)
+    Ac = oracle.Csr.from_synth(A)
+    plan = shiro.partition(Ad.row_ptr, Ad.col, A.n_rows, A.n_cols, A.P, A.p)
+    U, _ = shiro.select_rows(plan)
+    uc, off, cm = oracle.select(Ac)
+    knobs = {k: random_tuning(rng, walk=k != "sddmm") for k in ("spmm", "spmm_t", "sddmm", "partial_c", "aggregate_c")}
+    for k, t in knobs.items():
+        shiro.set_tuning(plan, k, N, dtype, **t)
+        if k in ("partial_c", "aggregate_c"):
+            shiro.set_tuning(plan, k, N, torch.float32, **t)
+    B = synth.dense(A.n_cols, N, seed, synth.STREAM_B)
+    G = synth.dense(max(Ac.M, 1), N, seed, synth.STREAM_DY)[: Ac.M]
+    Bd, Gd = B.to(dtype).to(dev), G.to(dtype).to(dev)
+    Bn, Gn = B.numpy(), G.numpy()
+    Bp = shiro.pack_B(plan, Bd)
+    Yref = oracle.spmm(Ac, Bn, None)
+    den = oracle.spmm(Ac, Bn, None, abs_mode=True)
+    Y = shiro.spmm(plan, Ad.vals, Bp)
+    assert oracle.rel_err(Y.float().cpu().numpy(), Yref, den) <= tol, knobs
+    dBp = torch.empty(U, N, dtype=dtype, device=dev)
+    dvals = torch.zeros(A.nnz, device=dev)
+    shiro.spmm_backward(plan, Ad.vals, Gd, Bp, dBpacked=dBp, dvals=dvals)
+    rdBp = oracle.spmm_t(Ac, Gn, cm, n_out=U)
+    rden = oracle.spmm_t(Ac, Gn, cm, n_out=U, abs_mode=True)
+    assert oracle.rel_err(dBp.float().cpu().numpy(), rdBp, rden) <= tol, knobs
+    rdv = oracle.sddmm(Ac, Gn, Bn, None)
+    rdvd = oracle.sddmm(Ac, Gn, Bn, None, abs_mode=True)
+    assert oracle.rel_err(dvals.cpu().numpy()[Ac.nz_begin:Ac.nz_begin + Ac.nnz_panel], rdv, rdvd) <= tol, knobs
+    # dvals alone (the sampled product's own kernel)
+    dv2 = torch.zeros_like(dvals)
+    shiro.spmm_backward(plan, Ad.vals, Gd, Bp, dvals=dv2)
+    assert oracle.rel_err(dv2.cpu().numpy()[Ac.nz_begin:Ac.nz_begin + Ac.nnz_panel], rdv, rdvd) <= tol, knobs
+    R, _ = shiro.select_c_rows(plan)
+    Cp = shiro.partial_c(plan, Ad.vals, Bd, R, out_dtype=torch.float32)
+    Yr = shiro.aggregate_c(plan, Cp)
+    assert oracle.rel_err(Yr.cpu().numpy(), Yref, den) <= tol, knobs
