@@ -2,8 +2,10 @@
 empty rows, empty and dense column blocks, single-column blocks and sizes
 that P does not divide, checked against routes that share nothing with the
 oracle's loops: a brute-force column scan for Cols(A^(p,q)) (Table 1), dense
-numpy products for the SpMM, its transpose and the sampled product, and the
-adjoint identity of L = <G, A B> for the gradients."""
+numpy products for the SpMM, its transpose and the sampled product, the
+adjoint identity of L = <G, A B> for the gradients, a (row, block) scan and
+dense block products for the row-based scheme, and exhaustive search for
+the minimum weighted vertex cover of the joint strategy."""
 import numpy as np
 from hypothesis import HealthCheck, given, settings
 from hypothesis import strategies as st
@@ -101,3 +103,54 @@ def test_products_against_dense(case):
     assert np.isclose(L, float(np.sum(dBp * Bp.astype(np.float64))), rtol=1e-10, atol=1e-10)
     vals = A.vals[A.nz_begin:A.nz_begin + A.nnz_panel].astype(np.float64)
     assert np.isclose(L, float(np.dot(vals, dv)), rtol=1e-10, atol=1e-10)
+
+
+@SETTINGS
+@given(panels())
+def test_row_based_against_scan_and_dense(case):
+    """Rows(A^(p,q)) by a (row, block) scan; the owner's partial rows are each
+    block's dense slice times B; their sum over blocks is the panel product."""
+    A, N, rng = case
+    rs, off = oracle.select_c_rows(A)
+    expect, counts = [], []
+    for q in range(A.P):
+        lo, hi = q * A.K, min(A.n_cols, (q + 1) * A.K)
+        rows_q = [i - A.row_begin for i in range(A.row_begin, A.row_end)
+                  if any(lo <= c < hi for c in A.col[A.row_ptr[i]:A.row_ptr[i + 1]])]
+        expect += rows_q
+        counts.append(len(rows_q))
+    assert rs.tolist() == expect
+    assert off.tolist() == np.concatenate([[0], np.cumsum(counts)]).tolist()
+    B = rng.standard_normal((A.n_cols, N)).astype(np.float32)
+    Cp = oracle.partial_c(A, B, rs, off)
+    D = panel_dense(A)
+    for q in range(A.P):
+        lo, hi = q * A.K, min(A.n_cols, (q + 1) * A.K)
+        sl = D[:, lo:hi] @ B[lo:hi].astype(np.float64)
+        assert np.allclose(Cp[off[q]:off[q + 1]], sl[rs[off[q]:off[q + 1]]], rtol=1e-12, atol=1e-12)
+    Y = oracle.aggregate_c(A, Cp, rs, off)
+    assert np.allclose(Y[:A.M], D @ B.astype(np.float64), rtol=1e-12, atol=1e-12)
+
+
+@settings(max_examples=80, deadline=None)
+@given(st.integers(1, 7), st.integers(1, 7), st.integers(0, 2**31 - 1), st.booleans())
+def test_cover_against_brute_force(n_left, n_right, seed, weighted):
+    """The max-flow cover of Sec. 5.3 is a vertex cover of minimum weight:
+    every edge is covered, and no subset of the vertices covers the edges
+    with less weight (exhaustive over all 2^(n_left + n_right) subsets)."""
+    rng = np.random.default_rng(seed)
+    m = rng.random((n_left, n_right)) < 0.4
+    edges = np.argwhere(m)
+    wl = rng.integers(1, 6, n_left) if weighted else np.ones(n_left, np.int64)
+    wr = rng.integers(1, 6, n_right) if weighted else np.ones(n_right, np.int64)
+    w, cl, cr = oracle.mvc_bipartite(n_left, n_right, edges, wl, wr)
+    assert all(cl[a] or cr[b] for a, b in edges)
+    assert w == int(wl[cl].sum() + wr[cr].sum())
+    best = None
+    V = n_left + n_right
+    for mask in range(1 << V):
+        sel = [(mask >> v) & 1 for v in range(V)]
+        if all(sel[a] or sel[n_left + b] for a, b in edges):
+            cost = sum(int(wl[v]) for v in range(n_left) if sel[v]) + sum(int(wr[v]) for v in range(n_right) if sel[n_left + v])
+            best = cost if best is None else min(best, cost)
+    assert w == (best if best is not None else 0)
