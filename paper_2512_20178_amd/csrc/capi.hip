@@ -383,6 +383,29 @@ static int time_candidate(hipStream_t s, F&& run, float* ms_out) {
   return rc;
 }
 
+// Chunk size at which a persistent grid of wg_per_cu workgroups per CU gives
+// each of its workers m chunks: merge items / (CUs * wg_per_cu * workers per
+// workgroup * m).  Workers are wavefronts, or lane groups for the nonzero
+// walk; the lanes a lane group uses follow from N as in the launch (the
+// fused backward always asks for one tile).  0 when the items are unknown.
+static int fit_chunk(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt, const shiro_tuning_t& t, int m) {
+  int64_t items;
+  if (kernel == SHIRO_KERNEL_SPMM || kernel == SHIRO_KERNEL_SDDMM) items = plan->rows + plan->nnz;
+  else if (kernel == SHIRO_KERNEL_SPMM_T) items = plan->U + plan->nnz;
+  else if (!plan->rb.built) return 0;
+  else if (kernel == SHIRO_KERNEL_PARTIAL_C) items = plan->rb.R + plan->nnz;
+  else items = plan->rows + plan->rb.R;
+  const int vec16 = dt == SHIRO_F32 ? 4 : 8;
+  const int vec = (N % vec16 == 0) ? vec16 : 1;
+  int lanes = kernel == SHIRO_KERNEL_SPMM_T ? 64 : t.lanes;
+  const int64_t need = ceil_div((int64_t)N, (int64_t)vec);
+  while (lanes > 8 && lanes / 2 >= need) lanes /= 2;
+  const int64_t wpb = kWavesPerBlock * (t.group_rows == 2 ? kWave / lanes : 1);
+  const int64_t workers = (int64_t)plan->num_cus * t.wg_per_cu * wpb * m;
+  const int64_t c = ceil_div(items, workers);
+  return (int)std::min<int64_t>(std::max<int64_t>(c, 16), 1 << 22);
+}
+
 static int tune_one(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt, TuneBuffers& b,
                     hipStream_t s) {
   const std::string key = tune_key(plan, kernel, N, dt);
@@ -437,9 +460,16 @@ static int tune_one(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt, Tune
           t.xcd_remap = xcd;
           SHIRO_TRY(consider(t));
         }
-  // stage 3: work size and depth again around the best layout
+  // stage 3: work size and depth again around the best layout, plus the
+  // chunk sizes that give every worker of a full persistent grid exactly one
+  // or two chunks (no tail round)
   const shiro_tuning_t base3 = best;
-  for (int chunk : {64, 128, 256, 512})
+  std::vector<int> chunks{64, 128, 256, 512};
+  for (int m : {1, 2}) {
+    const int fit = fit_chunk(plan, kernel, N, dt, base3, m);
+    if (fit > 0 && std::find(chunks.begin(), chunks.end(), fit) == chunks.end()) chunks.push_back(fit);
+  }
+  for (int chunk : chunks)
     for (int unroll : {1, 2, 4}) {
       shiro_tuning_t t = base3;
       t.chunk = chunk;
