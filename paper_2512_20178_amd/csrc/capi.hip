@@ -476,6 +476,15 @@ static int tune_one(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt, Tune
       t.unroll = unroll;
       SHIRO_TRY(consider(t));
     }
+  // stage 4: occupancy and fitted chunk together around the best layout
+  const shiro_tuning_t base4 = best;
+  for (int wg : {2, 4, 8, 16})
+    for (int m : {1, 2, 3}) {
+      shiro_tuning_t t = base4;
+      t.wg_per_cu = wg;
+      t.chunk = fit_chunk(plan, kernel, N, dt, t, m);
+      if (t.chunk > 0) SHIRO_TRY(consider(t));
+    }
   plan->tuning[TuneKey{kernel, N, (int)dt}] = best;
   cache_store(key, best);
   return SHIRO_OK;
