@@ -107,6 +107,35 @@ def test_products_against_dense(case):
 
 @SETTINGS
 @given(panels())
+def test_abs_denominators_against_dense(case):
+    """The error denominators |A||B|, |A|^T|G| and sum_j |G||B| (whole,
+    row-sampled and column-sampled forms) against dense products of
+    absolute values."""
+    A, N, rng = case
+    uc, off, cm = oracle.select(A)
+    U = len(uc)
+    B = rng.standard_normal((A.n_cols, N)).astype(np.float32)
+    G = rng.standard_normal((A.M, N)).astype(np.float32)
+    D = np.abs(panel_dense(A))
+    aB, aG = np.abs(B.astype(np.float64)), np.abs(G.astype(np.float64))
+    Bp = oracle.pack(B, uc)
+    den = D @ aB
+    assert np.allclose(oracle.spmm(A, Bp, cm, abs_mode=True), den, rtol=1e-12, atol=1e-12)
+    if A.M:
+        rows = rng.integers(0, A.M, size=min(A.M, 5))
+        assert np.allclose(oracle.spmm_rows(A, rows, Bp, cm, abs_mode=True), den[rows], rtol=1e-12, atol=1e-12)
+    den_t = D.T @ aG
+    assert np.allclose(oracle.spmm_t(A, G, cm, n_out=U, abs_mode=True), den_t[uc], rtol=1e-12, atol=1e-12)
+    if U:
+        t = rng.permutation(U)[: min(U, 5)]
+        assert np.allclose(oracle.spmm_t_sampled(A, G, cm, U, t, abs_mode=True), den_t[uc[t]],
+                           rtol=1e-12, atol=1e-12)
+    rr, cc = np.nonzero(D)
+    assert np.allclose(oracle.sddmm(A, G, Bp, cm, abs_mode=True), (aG @ aB.T)[rr, cc], rtol=1e-12, atol=1e-12)
+
+
+@SETTINGS
+@given(panels())
 def test_row_based_against_scan_and_dense(case):
     """Rows(A^(p,q)) by a (row, block) scan; the owner's partial rows are each
     block's dense slice times B; their sum over blocks is the panel product."""

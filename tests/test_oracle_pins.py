@@ -266,6 +266,75 @@ def test_spmm_abs_denominator():
     assert np.allclose(den, np.abs(dense_of(A)) @ np.abs(B.astype(np.float64)), rtol=1e-13)
 
 
+# The absolute-value forms are the denominators of every floating-point parity
+# check (componentwise |Y - Y*| / (|A||B|)): each is pinned against a dense
+# product of absolute values, on signed values and signed dense rows so that
+# dropping either absolute value, transposing the operands or reading the
+# wrong row changes the result.
+def test_abs_denominators_against_dense(case):
+    rng = np.random.default_rng(61)
+    N = 5
+    B = rng.standard_normal((case.n_cols, N)).astype(np.float32)
+    G = rng.standard_normal((case.M, N)).astype(np.float32)
+    uc, off, cm = oracle.select(case)
+    U = int(off[-1])
+    Bp = oracle.pack(B, uc)
+    D = np.abs(dense_of(case)[case.row_begin:case.row_end])
+    aB, aG = np.abs(B.astype(np.float64)), np.abs(G.astype(np.float64))
+    # |A|^T |G| onto B rows and onto packed rows
+    den_t = D.T @ aG
+    assert np.allclose(oracle.spmm_t(case, G, None, abs_mode=True), den_t, rtol=1e-12, atol=1e-12)
+    assert np.allclose(oracle.spmm_t(case, G, cm, n_out=U, abs_mode=True), den_t[uc], rtol=1e-12, atol=1e-12)
+    # the sampled form: rows of the packed result, in any order
+    if U:
+        t = rng.permutation(U)[: max(1, U // 2)]
+        assert np.allclose(oracle.spmm_t_sampled(case, G, cm, U, t, abs_mode=True), den_t[uc[t]],
+                           rtol=1e-12, atol=1e-12)
+    # sum_j |G[i(k), j]| |B[c(k), j]| at every nonzero, packed and direct
+    full = aG @ aB.T
+    rr, cc = np.nonzero(D)
+    assert np.allclose(oracle.sddmm(case, G, Bp, cm, abs_mode=True), full[rr, cc], rtol=1e-12, atol=1e-12)
+    assert np.allclose(oracle.sddmm(case, G, B, None, abs_mode=True), full[rr, cc], rtol=1e-12, atol=1e-12)
+    # rows of |A| |B|, in any order, packed and direct
+    den = D @ aB
+    rows = rng.permutation(case.M)[: max(1, case.M // 2)] if case.M else np.zeros(0, np.int64)
+    assert np.allclose(oracle.spmm_rows(case, rows, Bp, cm, abs_mode=True), den[rows], rtol=1e-12, atol=1e-12)
+    assert np.allclose(oracle.spmm_rows(case, rows, B, None, abs_mode=True), den[rows], rtol=1e-12, atol=1e-12)
+    assert np.allclose(oracle.spmm(case, Bp, cm, abs_mode=True), den, rtol=1e-12, atol=1e-12)
+
+
+def test_abs_denominators_bound_the_signed_forms():
+    """|sum a_k b_k| <= sum |a_k| |b_k| for every output, with equality when
+    every term is non-negative: each denominator is at least the magnitude of
+    its signed result, and equals it on non-negative data."""
+    A = oracle.Csr.from_synth(synth.small_rmat(9, 6, P=2, p=1, vals_lo=-1.0))
+    rng = np.random.default_rng(62)
+    N = 6
+    B = rng.standard_normal((A.n_cols, N)).astype(np.float32)
+    G = rng.standard_normal((A.M, N)).astype(np.float32)
+    uc, off, cm = oracle.select(A)
+    U = int(off[-1])
+    Bp = oracle.pack(B, uc)
+    pairs = [
+        (oracle.spmm(A, Bp, cm), oracle.spmm(A, Bp, cm, abs_mode=True)),
+        (oracle.spmm_t(A, G, cm, n_out=U), oracle.spmm_t(A, G, cm, n_out=U, abs_mode=True)),
+        (oracle.sddmm(A, G, Bp, cm), oracle.sddmm(A, G, Bp, cm, abs_mode=True)),
+    ]
+    for signed, den in pairs:
+        assert np.all(np.abs(signed) <= den * (1 + 1e-12) + 1e-300)
+        assert np.any(den > np.abs(signed) * (1 + 1e-6))  # signed data cancels somewhere
+    # non-negative data: the absolute forms are the signed forms
+    Ap = oracle.Csr(A.n_rows, A.n_cols, A.row_ptr, A.col, np.abs(A.vals), A.P, A.p)
+    aBp, aG = np.abs(Bp), np.abs(G)
+    assert np.array_equal(oracle.spmm(Ap, aBp, cm), oracle.spmm(A, Bp, cm, abs_mode=True))
+    assert np.array_equal(oracle.spmm_t(Ap, aG, cm, n_out=U), oracle.spmm_t(A, G, cm, n_out=U, abs_mode=True))
+    assert np.array_equal(oracle.sddmm(Ap, aG, aBp, cm), oracle.sddmm(A, G, Bp, cm, abs_mode=True))
+    t = np.arange(0, U, 7)
+    assert np.array_equal(oracle.spmm_t_sampled(Ap, aG, cm, U, t), oracle.spmm_t_sampled(A, G, cm, U, t, abs_mode=True))
+    rows = np.arange(0, A.M, 5)
+    assert np.array_equal(oracle.spmm_rows(Ap, rows, aBp, cm), oracle.spmm_rows(A, rows, Bp, cm, abs_mode=True))
+
+
 # ----------------------------------------------------------------------------
 # backward: dB = A^T G, dvals = (G B^T) sampled at the nonzeros
 # ----------------------------------------------------------------------------
