@@ -225,7 +225,7 @@ def main():
         if pmc.get("src_hash") == src_hash("csrc/spmm.hip", "csrc/common.hpp", "csrc/capi.hip", "tuning_mi355x.txt"):
             traffic = pmc.get("hbm_bytes_per_launch")
     # the product kernel each op ran, from the plan's tuning (group_rows)
-    kname = {0: "k_spmm", 1: "k_spmm_grp", 2: "k_spmm_flat"}
+    kname = {0: "k_spmm", 1: "k_spmm_grp", 2: "k_spmm_flat", 3: "k_spmm_win"}
     kf = kname[shiro.get_tuning(plan, "spmm", N, tdt)["group_rows"]]
     kb = kname[shiro.get_tuning(plan, "spmm_t", N, tdt)["group_rows"]]
     kernels_of = {"pack_B": "k_pack", "spmm": f"{kf} + k_fixup",

@@ -137,8 +137,10 @@ typedef struct {
   int32_t unroll;    /* nonzeros in flight per lane group: 1, 2 or 4           */
   int32_t group_rows; /* 0: a wavefront per row; 1: each lane group of a
                        * wavefront owns its own rows; 2: each lane group walks
-                       * its own chunks nonzero by nonzero across row ends (not
-                       * for the sampled product, SHIRO_KERNEL_SDDMM)          */
+                       * its own chunks nonzero by nonzero across row ends;
+                       * 3: the same walk with its index, row and value streams
+                       * loaded a window of `lanes` nonzeros at a time (2 and 3
+                       * not for the sampled product, SHIRO_KERNEL_SDDMM)      */
   int32_t xcd_remap; /* 1: give each XCD a contiguous range of work            */
   int32_t wg_per_cu; /* persistent grid: workgroups per compute unit           */
 } shiro_tuning_t;

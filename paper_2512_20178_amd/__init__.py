@@ -112,8 +112,38 @@ def _ld(t: torch.Tensor) -> int:
 
 
 def _dev(t: torch.Tensor):
-    if not t.is_cuda:
-        raise ValueError("operands must live on the GPU")
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("operands must be tensors on the GPU")
+
+
+def _mat(t: Optional[torch.Tensor], name: str, min_rows: int, N: int, dtypes=None):
+    """Check a dense operand before its pointer reaches the library: on the
+    GPU, 2-D, at least min_rows rows of exactly N columns, row-major with unit
+    column stride, of an allowed dtype."""
+    if t is None:
+        return
+    _dev(t)
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D")
+    if t.shape[0] < min_rows or t.shape[1] != N:
+        raise ValueError(f"{name} must have at least {min_rows} rows and {N} columns, got {tuple(t.shape)}")
+    if dtypes is not None and t.dtype not in dtypes:
+        raise TypeError(f"{name} must be one of {dtypes}, got {t.dtype}")
+    _ld(t)
+
+
+def _vec(t: Optional[torch.Tensor], name: str, min_numel: int):
+    """Check a float32 vector indexed like the CSR's nonzeros (vals, dvals)."""
+    if t is None:
+        return
+    _dev(t)
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < min_numel:
+        raise ValueError(f"{name} must have at least {min_numel} entries (indexed like the CSR's nonzeros), "
+                         f"got {t.numel()}")
 
 
 def version() -> int:
@@ -123,10 +153,14 @@ def version() -> int:
 class Plan:
     """Library-owned plan of rank p's panel (freed when garbage collected)."""
 
-    def __init__(self, handle: int, device: torch.device):
+    def __init__(self, handle: int, device: torch.device, value_extent: Optional[int] = None):
         self._h = ctypes.c_void_p(handle)
         self.device = device
         self._graphs = []
+        inf = self.info()
+        # entries of the CSR's value array the plan reads (vals, dvals)
+        self.value_extent = value_extent if value_extent is not None else inf["nz_begin"] + inf["nnz"]
+        self.R = None  # sum of |Rows(A^(p,q))| once select_c_rows ran
 
     @property
     def handle(self):
@@ -181,6 +215,7 @@ def partition(row_ptr: torch.Tensor, col: torch.Tensor, n_rows: int, n_cols: int
         raise TypeError("row_ptr must be int64 and col int32")
     if row_ptr.numel() != n_rows + 1:
         raise ValueError("row_ptr must have n_rows + 1 entries")
+    _dev(col)
     h = ctypes.c_void_p()
     nnz = col.numel()
     _lib.check(_L().shiro_partition(int(n_rows), int(n_cols), int(nnz), _ptr(row_ptr.contiguous()),
@@ -195,16 +230,26 @@ def partition_subset(row_ptr: torch.Tensor, col: torch.Tensor, n_rows: int, n_co
     """Plan over the panel's nonzeros k with keep[k] == keep_value (keep: uint8
     on the device, one entry per nonzero of panel p)."""
     _dev(row_ptr)
+    _dev(col)
     _dev(keep)
     if row_ptr.dtype != torch.int64 or col.dtype != torch.int32 or keep.dtype != torch.uint8:
         raise TypeError("row_ptr int64, col int32, keep uint8")
+    if row_ptr.numel() != n_rows + 1:
+        raise ValueError("row_ptr must have n_rows + 1 entries")
+    if P < 1 or not 0 <= p < P:
+        raise ValueError("need P >= 1 and 0 <= p < P")
+    M = -(-n_rows // P)
+    r0, r1 = min(p * M, n_rows), min(p * M + M, n_rows)
+    nz0, nz1 = int(row_ptr[r0].item()), int(row_ptr[r1].item())
+    if keep.numel() < nz1 - nz0:
+        raise ValueError(f"keep must have one entry per panel nonzero ({nz1 - nz0}), got {keep.numel()}")
     h = ctypes.c_void_p()
     nnz = col.numel()
     _lib.check(_L().shiro_partition_subset(int(n_rows), int(n_cols), int(nnz), _ptr(row_ptr.contiguous()),
                                            _ptr(col.contiguous()) if nnz else None, _ptr(keep.contiguous()),
                                            int(keep_value), int(P), int(p), _lib.CHECK_CSR if check else 0,
                                            ctypes.c_void_p(_stream(stream)), ctypes.byref(h)))
-    return Plan(h.value, row_ptr.device)
+    return Plan(h.value, row_ptr.device, value_extent=nz1)
 
 
 def select_rows(plan: Plan, stream=None) -> Tuple[int, list]:
@@ -242,13 +287,18 @@ def block_nnz(plan: Plan, stream=None) -> torch.Tensor:
 
 def pack_B(plan: Plan, B: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     """Bpacked[u] = B[unique_cols[u]] (bit-exact), shape U x N."""
+    inf = plan.info()
+    U = inf["U"]
+    if U < 0:
+        raise ShiroError(-6, "pack_B: call select_rows first")
     _dev(B)
-    U = plan.info()["U"]
+    if B.dim() != 2:
+        raise ValueError("B must be 2-D")
     N = B.shape[1]
+    _mat(B, "B", inf["n_cols"], N, tuple(_DT))
     if out is None:
         out = torch.empty(U, N, dtype=B.dtype, device=B.device)
-    if out.dtype != B.dtype or out.shape[0] < U or out.shape[1] != N:
-        raise ValueError("out must be U x N with B's dtype")
+    _mat(out, "out", U, N, (B.dtype,))
     _lib.check(_L().shiro_pack_B(plan.handle, _ptr(B), _ld(B), N, _dt(B.dtype), _ptr(out), _ld(out),
                                  ctypes.c_void_p(_stream(stream))))
     return out
@@ -257,14 +307,20 @@ def pack_B(plan: Plan, B: torch.Tensor, out: Optional[torch.Tensor] = None, stre
 def spmm(plan: Plan, vals: torch.Tensor, Bpacked: torch.Tensor, out: Optional[torch.Tensor] = None,
          out_dtype: Optional[torch.dtype] = None, mode: str = "batched", stream=None) -> torch.Tensor:
     """Y = A^(p,:) Bpacked (rows x N); vals is the CSR's float32 value array."""
+    inf = plan.info()
+    rows = inf["rows"]
     _dev(Bpacked)
-    if vals.dtype != torch.float32:
-        raise TypeError("vals must be float32")
-    rows = plan.info()["rows"]
+    if Bpacked.dim() != 2:
+        raise ValueError("Bpacked must be 2-D")
     N = Bpacked.shape[1]
+    _mat(Bpacked, "Bpacked", max(inf["U"], 0), N, tuple(_DT))
+    _vec(vals, "vals", plan.value_extent)
     out_dtype = out_dtype or Bpacked.dtype
     if out is None:
         out = torch.empty(rows, N, dtype=out_dtype, device=Bpacked.device)
+    _mat(out, "out", rows, N, tuple(_DT))
+    if mode not in ("batched", "per_block"):
+        raise ValueError("mode must be 'batched' or 'per_block'")
     m = {"batched": _lib.MODE_BATCHED, "per_block": _lib.MODE_PER_BLOCK}[mode]
     _lib.check(_L().shiro_spmm(plan.handle, _ptr(vals), _ptr(Bpacked), _ld(Bpacked), N, _dt(Bpacked.dtype),
                                _ptr(out), _ld(out), _dt(out.dtype), m, ctypes.c_void_p(_stream(stream))))
@@ -279,12 +335,22 @@ def spmm_backward(plan: Plan, vals: torch.Tensor, dY: torch.Tensor, Bpacked: Opt
     Pass the output tensors to compute; None skips an output.  With
     dB_overwrite the rows dB[unique_cols] are overwritten instead of added to
     (the other rows are left as they are)."""
+    inf = plan.info()
     _dev(dY)
+    if dY.dim() != 2:
+        raise ValueError("dY must be 2-D")
     N = dY.shape[1]
     dt = _dt(dY.dtype)
-    for t in (Bpacked, dBpacked, dB):
-        if t is not None and t.dtype != dY.dtype:
-            raise TypeError("dY, Bpacked, dBpacked and dB share one dtype")
+    U = max(inf["U"], 0)
+    _mat(dY, "dY", inf["rows"], N)
+    _mat(Bpacked, "Bpacked", U, N, (dY.dtype,))
+    _mat(dBpacked, "dBpacked", U, N, (dY.dtype,))
+    _mat(dB, "dB", inf["n_cols"], N, (dY.dtype,))
+    if dBpacked is not None or dB is not None:
+        _vec(vals, "vals", plan.value_extent)
+    _vec(dvals, "dvals", plan.value_extent)
+    if dvals is not None and Bpacked is None:
+        raise ValueError("dvals needs Bpacked")
     _lib.check(_L().shiro_spmm_backward(
         plan.handle, _ptr(vals), _ptr(dY), _ld(dY), _ptr(Bpacked), _ld(Bpacked) if Bpacked is not None else N,
         N, dt, _ptr(dBpacked), _ld(dBpacked) if dBpacked is not None else N, _ptr(dB),
@@ -301,6 +367,7 @@ def select_c_rows(plan: Plan, stream=None) -> Tuple[int, list]:
     R = ctypes.c_int64()
     per = (ctypes.c_int64 * max(plan.P, 1))()
     _lib.check(_L().shiro_select_c_rows(plan.handle, ctypes.c_void_p(_stream(stream)), ctypes.byref(R), per))
+    plan.R = R.value
     return R.value, list(per[:plan.P])
 
 
@@ -316,9 +383,16 @@ def partial_c(plan: Plan, vals: torch.Tensor, B: torch.Tensor, R: int, out: Opti
               out_dtype=None, stream=None) -> torch.Tensor:
     """Cp[e] = sum over block q's nonzeros of row Rows_q[t] of vals[k] * B[col[k]] (R x N)."""
     _dev(B)
+    if B.dim() != 2:
+        raise ValueError("B must be 2-D")
     N = B.shape[1]
+    _mat(B, "B", plan.info()["n_cols"], N, tuple(_DT))
+    _vec(vals, "vals", plan.value_extent)
+    if getattr(plan, "R", None) is not None and R != plan.R:
+        raise ValueError(f"R must be the plan's |Rows| total {plan.R}, got {R}")
     if out is None:
         out = torch.empty(R, N, dtype=out_dtype or B.dtype, device=B.device)
+    _mat(out, "out", R, N, tuple(_DT))
     _lib.check(_L().shiro_partial_c(plan.handle, _ptr(vals), _ptr(B), _ld(B), N, _dt(B.dtype), _ptr(out), _ld(out),
                                     _dt(out.dtype), ctypes.c_void_p(_stream(stream))))
     return out
@@ -329,11 +403,15 @@ def aggregate_c(plan: Plan, Cp: torch.Tensor, out: Optional[torch.Tensor] = None
     """Y[i] = sum over blocks (ascending) of row i's partial rows (rows x N);
     with accumulate the sums are added to `out`."""
     _dev(Cp)
+    if Cp.dim() != 2:
+        raise ValueError("Cp must be 2-D")
     N = Cp.shape[1]
+    _mat(Cp, "Cp", getattr(plan, "R", None) or 0, N, tuple(_DT))
     if out is None:
         if accumulate:
             raise ValueError("accumulate needs out")
         out = torch.empty(plan.rows, N, dtype=out_dtype or Cp.dtype, device=Cp.device)
+    _mat(out, "out", plan.rows, N, tuple(_DT))
     _lib.check(_L().shiro_aggregate_c(plan.handle, _ptr(Cp), _ld(Cp), N, _dt(Cp.dtype), _ptr(out), _ld(out),
                                       _dt(out.dtype), _lib.AGG_ACCUMULATE if accumulate else 0,
                                       ctypes.c_void_p(_stream(stream))))

@@ -106,10 +106,16 @@ bool stream_capturing(hipStream_t s) {
   return st == hipStreamCaptureStatusActive;
 }
 
+void retire_buffer(shiro_plan plan, void* p) {
+  if (!p) return;
+  if (plan->graphs.empty()) dev_free(p);
+  else plan->retired.push_back(p);
+}
+
 int ensure_scratch(shiro_plan plan, int64_t bytes) {
   if (plan->scratch_bytes >= bytes) return SHIRO_OK;
   SHIRO_HIP(hipDeviceSynchronize());  // earlier setup kernels may still use it
-  dev_free(plan->scratch);
+  retire_buffer(plan, plan->scratch);
   plan->scratch = nullptr;
   plan->scratch_bytes = 0;
   SHIRO_TRY(dev_alloc(&plan->scratch, bytes));
@@ -168,7 +174,7 @@ int ensure_carry(shiro_plan plan, int64_t elems, bool allocate) {
   if (plan->carry_elems >= elems) return SHIRO_OK;
   if (!allocate) return set_error(SHIRO_ERR_CAPTURING, "carry buffer not prepared before capture");
   SHIRO_HIP(hipDeviceSynchronize());
-  dev_free(plan->carry);
+  retire_buffer(plan, plan->carry);
   plan->carry = nullptr;
   plan->carry_elems = 0;
   SHIRO_TRY(dev_alloc_n(&plan->carry, elems));
@@ -180,7 +186,7 @@ int ensure_acc32(shiro_plan plan, int64_t elems, bool allocate) {
   if (plan->acc32_elems >= elems) return SHIRO_OK;
   if (!allocate) return set_error(SHIRO_ERR_CAPTURING, "per-block accumulator not prepared before capture");
   SHIRO_HIP(hipDeviceSynchronize());
-  dev_free(plan->acc32);
+  retire_buffer(plan, plan->acc32);
   plan->acc32 = nullptr;
   plan->acc32_elems = 0;
   SHIRO_TRY(dev_alloc_n(&plan->acc32, elems));
@@ -221,8 +227,8 @@ int validate_tuning(int kernel, int32_t, shiro_dtype, const shiro_tuning_t& t) {
     return set_error(SHIRO_ERR_INVALID_ARG, "tuning: lanes must be 8, 16, 32 or 64");
   if (t.unroll != 1 && t.unroll != 2 && t.unroll != 4)
     return set_error(SHIRO_ERR_INVALID_ARG, "tuning: unroll must be 1, 2 or 4");
-  if (t.group_rows < 0 || t.group_rows > 2) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: group_rows must be 0, 1 or 2");
-  if (t.group_rows == 2 && kernel == SHIRO_KERNEL_SDDMM)
+  if (t.group_rows < 0 || t.group_rows > 3) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: group_rows must be 0, 1, 2 or 3");
+  if (t.group_rows >= 2 && kernel == SHIRO_KERNEL_SDDMM)
     return set_error(SHIRO_ERR_INVALID_ARG, "tuning: the sampled product has no nonzero walk (group_rows 0 or 1)");
   if (t.xcd_remap != 0 && t.xcd_remap != 1) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: xcd_remap must be 0 or 1");
   if (t.wg_per_cu < 1 || t.wg_per_cu > 32) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: wg_per_cu outside [1, 32]");
@@ -288,6 +294,7 @@ static void plan_free(shiro_plan plan) {
   dev_free(plan->carry);
   dev_free(plan->acc32);
   dev_free(plan->scratch);
+  for (void* p : plan->retired) dev_free(p);
   if (plan->h_pinned) (void)hipHostFree(plan->h_pinned);
   delete plan;
 }
@@ -400,7 +407,7 @@ static int fit_chunk(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt, con
   int lanes = kernel == SHIRO_KERNEL_SPMM_T ? 64 : t.lanes;
   const int64_t need = ceil_div((int64_t)N, (int64_t)vec);
   while (lanes > 8 && lanes / 2 >= need) lanes /= 2;
-  const int64_t wpb = kWavesPerBlock * (t.group_rows == 2 ? kWave / lanes : 1);
+  const int64_t wpb = kWavesPerBlock * (t.group_rows >= 2 ? kWave / lanes : 1);
   const int64_t workers = (int64_t)plan->num_cus * t.wg_per_cu * wpb * m;
   const int64_t c = ceil_div(items, workers);
   return (int)std::min<int64_t>(std::max<int64_t>(c, 16), 1 << 22);
@@ -449,7 +456,7 @@ static int tune_one(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt, Tune
   // stage 2: lane width, occupancy, XCD placement around the best
   const shiro_tuning_t base = best;
   const bool walk = kernel != SHIRO_KERNEL_SDDMM;
-  for (int grp = 0; grp <= (walk ? 2 : 1); ++grp)
+  for (int grp = 0; grp <= (walk ? 3 : 1); ++grp)
     for (int lanes : {64, 32, 16})
       for (int wg : {2, 4, 8, 16})
         for (int xcd : {0, 1}) {

@@ -136,6 +136,9 @@ struct shiro_plan_s {
 
   std::map<shiro::TuneKey, shiro_tuning_t> tuning;
   std::vector<hipGraphExec_t> graphs;
+  // buffers replaced by larger ones after a graph was captured: a captured
+  // graph may still name them, so they are freed with the plan only
+  std::vector<void*> retired;
   hipGraph_t capture_graph = nullptr;
 };
 
@@ -149,6 +152,9 @@ int dev_alloc_n(T** p, int64_t n) {
   return dev_alloc(reinterpret_cast<void**>(p), n * (int64_t)sizeof(T));
 }
 int ensure_scratch(shiro_plan plan, int64_t bytes);
+// Give up a plan buffer that is being replaced: freed now, or kept until the
+// plan is destroyed when a graph captured earlier may still use it.
+void retire_buffer(shiro_plan plan, void* p);
 bool stream_capturing(hipStream_t s);
 
 // ---- scan.hip ---------------------------------------------------------------

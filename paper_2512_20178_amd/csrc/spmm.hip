@@ -609,6 +609,208 @@ __global__ __launch_bounds__(kBlock) void k_spmm_flat(SHIRO_SPMM_PARAMS(TIN, TOU
   }
 }
 
+// Nonzero walk with windowed index streams.  Same walk, carries and output
+// order as k_spmm_flat, but a lane group no longer issues one vector load per
+// nonzero for each of its index, row-id and value streams: every LANES steps'
+// worth of those (a window of LANES consecutive nonzeros) come in with one
+// coalesced load per stream, lane li holding nonzero kw + li, and each step
+// takes its UNROLL slots from the window by lane permutes (ds_bpermute, the
+// LDS crossbar, not the texture path).  On gfx950 a wavefront-wide vector
+// load costs the texture addresser about the same whether it fetches 4 or 16
+// bytes per lane, and the per-nonzero index loads outnumbered the row
+// gathers three to one.  The window after the current one is loaded a whole
+// window ahead.  With DOT, the dense row D[r] is loaded only when the row
+// changes (runs of a packed column's nonzeros share it), and the dots are
+// collected in the window's lanes and written with one store per window.
+template <typename T>
+__device__ __forceinline__ T lane_pull(int src_lane, T v) {
+  static_assert(sizeof(T) == 4, "32-bit values");
+  return __builtin_bit_cast(T, __builtin_amdgcn_ds_bpermute(src_lane << 2, __builtin_bit_cast(int, v)));
+}
+
+template <typename TIN, typename TOUT, int LANES, int VEC, int UNROLL, bool DOT, int SCAT>
+__global__ __launch_bounds__(kBlock) void k_spmm_win(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
+  constexpr int G = kWave / LANES;
+  constexpr int WIN = LANES;          // nonzeros per window and lane group
+  constexpr int WS = WIN / UNROLL;    // steps per window
+  static_assert(WIN % UNROLL == 0, "window");
+  const int lane = lane_id();
+  const int g = lane / LANES;
+  const int li = lane % LANES;
+  const int base_lane = g * LANES;
+  const int64_t c = (int64_t)blockIdx.y * (LANES * VEC) + (int64_t)li * VEC;
+  const bool cvalid = c < N;
+  const int64_t cl = cvalid ? c : 0;
+
+  const int64_t worker = (int64_t)uniform(logical_block(xcd_remap) * kWavesPerBlock + wave_id()) * G + g;
+  const int64_t wb = worker * cpw;
+  const int64_t we = wb + cpw < W ? wb + cpw : W;
+  if (wb >= we) return;  // whole lane groups leave; the others permute inside their own lanes only
+  for (int64_t w = wb; w < we; ++w) {
+    const int32_t i0 = chunk_row[w], i1 = chunk_row[w + 1];
+    const int64_t j0 = chunk_nz[w], j1 = chunk_nz[w + 1];
+    if (i0 >= R) break;
+    const bool has_head = j0 > ptr[i0];
+    const int32_t row_end = i1 < R ? i1 : R;
+    int32_t next = has_head ? i0 + 1 : i0;
+    float* const head_slot = carry + (w * 2) * N + c;
+    float* const tail_slot = carry + (w * 2 + 1) * N + c;
+    if (has_head && ptr[i0 + 1] <= j0 && cvalid) {  // row i0 holds nothing here
+      float z[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) z[e] = 0.f;
+      Elem<float>::template store<VEC>(head_slot, z);
+    }
+    auto put = [&](int32_t r, int32_t sidx, const float(&a)[VEC], bool zero) {
+      if (out) Elem<TOUT>::template store_nt<VEC>(out + (int64_t)r * ldo + c, a);
+      if constexpr (SCAT == 1) {
+        if (!zero) {
+          float pre[VEC];
+          Elem<TOUT>::template load<VEC>(scat + (int64_t)sidx * lds + c, pre);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) pre[e] += a[e];
+          Elem<TOUT>::template store<VEC>(scat + (int64_t)sidx * lds + c, pre);
+        }
+      } else if constexpr (SCAT == 2) {
+        Elem<TOUT>::template store_nt<VEC>(scat + (int64_t)sidx * lds + c, a);
+      }
+    };
+    auto zero_rows = [&](int32_t lim) {
+      for (; next < lim; ++next) {
+        if (!cvalid) continue;
+        float z[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) z[e] = 0.f;
+        put(next, SCAT ? scat_idx[next] : 0, z, true);
+      }
+    };
+    int32_t cur = -1, scur = 0;
+    float acc[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
+    auto flush = [&]() {
+      if (!cvalid) return;
+      if (cur == i0 && has_head) Elem<float>::template store<VEC>(head_slot, acc);
+      else if (cur == i1) Elem<float>::template store<VEC>(tail_slot, acc);
+      else put(cur, scur, acc, false);
+    };
+    if (j0 < j1) {
+      // window q of the chunk: lane li holds nonzero j0 + q WIN + li (clamped
+      // to the chunk's last nonzero; clamped slots are masked below)
+      auto wload = [&](int64_t kw, int32_t& wi, int32_t& wr, float& wv, int32_t& wsc) {
+        const int64_t kk = kw + li;
+        const int64_t kc = kk < j1 ? kk : j1 - 1;
+        wi = idx[kc];
+        wr = rid[kc];
+        wv = vals[kc];
+        if constexpr (SCAT != 0) wsc = scat_idx[wr];
+      };
+      int32_t ci, cr, csc = 0, ni, nr, nsc = 0;
+      float cv, nv;
+      wload(j0, ci, cr, cv, csc);
+      wload(j0 + WIN, ni, nr, nv, nsc);
+      // slots of the first step
+      int32_t xi[UNROLL], ri[UNROLL], sc[UNROLL];
+      float v[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        xi[u] = lane_pull(base_lane + u, ci);
+        ri[u] = lane_pull(base_lane + u, cr);
+        v[u] = lane_pull(base_lane + u, cv);
+        sc[u] = SCAT ? lane_pull(base_lane + u, csc) : 0;
+      }
+      float dl[DOT ? VEC : 1];  // D row of the previous slot and its row
+      int32_t dr = -1;
+      float mydot = 0.f;        // this lane's nonzero of the window: its dot
+      int s = 0;                // step inside the window
+      for (int64_t k = j0; k < j1; k += UNROLL) {
+        bool ok[UNROLL];
+        float x[UNROLL][VEC];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          ok[u] = k + u < j1;
+          Elem<TIN>::template load<VEC>(X + (int64_t)xi[u] * ldx + cl, x[u]);
+        }
+        float d[DOT ? UNROLL : 1][VEC];
+        if constexpr (DOT) {
+#pragma unroll
+          for (int u = 0; u < UNROLL; ++u) {
+            const int32_t rp = u == 0 ? dr : ri[u - 1];
+            if (ri[u] != rp) {
+              Elem<TIN>::template load_nt<VEC>(D + (int64_t)ri[u] * ldd + cl, d[u]);
+            } else {
+#pragma unroll
+              for (int e = 0; e < VEC; ++e) d[u][e] = u == 0 ? dl[e] : d[u - 1][e];
+            }
+          }
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) dl[e] = d[UNROLL - 1][e];
+          dr = ri[UNROLL - 1];
+        }
+        // the next step's slots: the current window, or the next one when
+        // this step ends the window (then the windows move up by one)
+        const int sn = s + 1 == WS ? 0 : s + 1;
+        if (sn == 0) {
+          ci = ni; cr = nr; cv = nv; csc = nsc;
+          wload(k + UNROLL + WIN, ni, nr, nv, nsc);
+        }
+        int32_t xin[UNROLL], rin[UNROLL], scn[UNROLL];
+        float vn[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          const int src = base_lane + sn * UNROLL + u;
+          xin[u] = lane_pull(src, ci);
+          rin[u] = lane_pull(src, cr);
+          vn[u] = lane_pull(src, cv);
+          scn[u] = SCAT ? lane_pull(src, csc) : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          if (ok[u] && ri[u] != cur) {
+            if (cur >= 0) flush();
+            zero_rows(ri[u]);
+            cur = ri[u];
+            scur = sc[u];
+            if (next <= cur) next = cur + 1;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
+          }
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) {
+            const float t = fmaf(v[u], x[u][e], acc[e]);
+            acc[e] = ok[u] ? t : acc[e];
+          }
+          if constexpr (DOT) {
+            float q = 0.f;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) q = fmaf(d[u][e], x[u][e], q);
+            q = group_sum<LANES>(cvalid ? q : 0.f);
+            q = lane_pull(base_lane + LANES - 1, q);
+            mydot = li == s * UNROLL + u ? q : mydot;
+          }
+        }
+        if constexpr (DOT) {
+          // the window's dots, one store per window
+          if (sn == 0 || k + UNROLL >= j1) {
+            const int64_t kd = k - (int64_t)s * UNROLL + li;
+            if (kd < j1 && kd <= k + UNROLL - 1) dot_out[kd] = mydot;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          xi[u] = xin[u];
+          ri[u] = rin[u];
+          v[u] = vn[u];
+          sc[u] = scn[u];
+        }
+        s = sn;
+      }
+    }
+    if (cur >= 0) flush();
+    zero_rows(row_end);
+  }
+}
+
 // Rows cut by chunk boundaries.  split[3 i] = first chunk ws, split[3 i + 1]
 // = last chunk we, split[3 i + 2] = row r.  The row's pieces are the tail
 // slot of ws and the head slots of ws+1 .. we, summed in that order.  The
@@ -1090,7 +1292,9 @@ template <typename TIN, typename TOUT, int VEC, bool DOT, int SCAT>
 int spmm_dispatch(const shiro_tuning_t& t, dim3 grid, hipStream_t s, const SpmmArgs& a) {
 #define SHIRO_SPMM_CASE(L, U)                                                                          \
   if (t.lanes == L && t.unroll == U) {                                                                 \
-    if (t.group_rows == 2 && a.rid)                                                                    \
+    if (t.group_rows == 3 && a.rid)                                                                    \
+      k_spmm_win<TIN, TOUT, L, VEC, U, DOT, SCAT><<<grid, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a)); \
+    else if (t.group_rows == 2 && a.rid)                                                               \
       k_spmm_flat<TIN, TOUT, L, VEC, U, DOT, SCAT><<<grid, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a)); \
     else if (t.group_rows)                                                                             \
       k_spmm_grp<TIN, TOUT, L, VEC, U, DOT, SCAT><<<grid, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a)); \
@@ -1140,7 +1344,7 @@ int run_spmm_family(shiro_plan plan, shiro_tuning_t t, const WorkList* wl, SpmmA
   t.lanes = effective_lanes(t.lanes, a.N, vec);
   unsigned nb;
   // the nonzero walk gives each lane group its own chunks
-  const int32_t workers = (t.group_rows == 2 && a.rid) ? kWavesPerBlock * (kWave / t.lanes) : kWavesPerBlock;
+  const int32_t workers = (t.group_rows >= 2 && a.rid) ? kWavesPerBlock * (kWave / t.lanes) : kWavesPerBlock;
   SHIRO_TRY(grid_waves(plan, t, wl->W, workers, &a.chunks_per_wave, &nb));
   const int ntiles = (int)ceil_div(a.N, (int64_t)t.lanes * vec);
   a.xcd_remap = t.xcd_remap;
@@ -1479,12 +1683,12 @@ int launch_spmm(shiro_plan plan, const shiro_tuning_t& t, const float* vals, con
   if (plan->rows == 0 || N == 0) return SHIRO_OK;
   const WorkList* wl;
   SHIRO_TRY(ensure_rows_work(plan, t.chunk, !stream_capturing(s), s, &wl));
-  if (t.group_rows == 2) SHIRO_TRY(ensure_row_rid(plan, !stream_capturing(s), s));
+  if (t.group_rows >= 2) SHIRO_TRY(ensure_row_rid(plan, !stream_capturing(s), s));
   SHIRO_TRY(ensure_carry(plan, (int64_t)wl->W * 2 * N, !stream_capturing(s)));
   const float* v = plan_values(plan, vals, s);
   SHIRO_LAUNCH_CHECK();
   return launch_pattern(plan, t, wl, plan->row_ptr, plan->colmap, v, plan->rows, X, ldx, N, in_dt, Y, ldy,
-                        out_dt, s, nullptr, t.group_rows == 2 ? plan->row_rid : nullptr);
+                        out_dt, s, nullptr, t.group_rows >= 2 ? plan->row_rid : nullptr);
 }
 
 int build_rowbased(shiro_plan plan, hipStream_t s) {

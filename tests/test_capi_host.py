@@ -153,3 +153,42 @@ def test_mvc_bipartite_argument_errors(lib):
     assert lib.shiro_mvc_bipartite(2, 2, 1, left, right, neg, None, cl, cr, c.byref(w)) == -1
     assert "negative" in _err(lib)
     assert lib.shiro_mvc_bipartite(-1, 2, 0, None, None, None, None, cl, cr, c.byref(w)) == -1
+
+
+class _FakePlan:
+    """Stands in for a Plan in binding checks that never reach the library."""
+
+    def __init__(self, **info):
+        base = dict(n_rows=8, n_cols=8, P=1, p=0, M=8, K=8, row_begin=0, rows=8, nz_begin=0, nnz=10, U=5)
+        base.update(info)
+        self._info = base
+        self.value_extent = base["nz_begin"] + base["nnz"]
+        self.R = None
+        self.handle = ctypes.c_void_p(0)
+        self.rows = base["rows"]
+
+    def info(self):
+        return dict(self._info)
+
+
+def test_binding_rejects_host_operands_before_any_call():
+    """CPU tensors never become device pointers: every compute wrapper
+    raises before it calls into the library (the fake plan's NULL handle
+    would fail any library call with INVALID_ARG instead)."""
+    import torch
+
+    import paper_2512_20178_amd as shiro
+
+    plan = _FakePlan()
+    B = torch.zeros(8, 4)
+    vals = torch.zeros(10)
+    with pytest.raises(ValueError, match="on the GPU"):
+        shiro.pack_B(plan, B)
+    with pytest.raises(ValueError, match="on the GPU"):
+        shiro.spmm(plan, vals, torch.zeros(5, 4))
+    with pytest.raises(ValueError, match="on the GPU"):
+        shiro.spmm_backward(plan, vals, torch.zeros(8, 4), torch.zeros(5, 4), dB=torch.zeros(8, 4))
+    with pytest.raises(ValueError, match="on the GPU"):
+        shiro.partial_c(plan, vals, B, 3)
+    with pytest.raises(ValueError, match="on the GPU"):
+        shiro.aggregate_c(plan, torch.zeros(3, 4))

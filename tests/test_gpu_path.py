@@ -308,8 +308,10 @@ def test_tunings_all_correct(shiro, run, knobs):
     dict(chunk=128, lanes=64, unroll=4),
     dict(chunk=2048, lanes=32, unroll=2, wg_per_cu=1),
 ])
-def test_nonzero_walk_correct(shiro, run, knobs):
-    """The nonzero walk (group_rows 2) of every kernel that has it: forward,
+@pytest.mark.parametrize("walk", [2, 3])
+def test_nonzero_walk_correct(shiro, run, knobs, walk):
+    """The nonzero walk (group_rows 2, and 3 with windowed index streams) of
+    every kernel that has it: forward,
     transposed product, partial rows and their sum.  Small chunks cut rows
     into many carried pieces; with few workers each lane group walks a long
     run of chunks (indices loaded one step ahead across chunk ends); rows
@@ -320,7 +322,7 @@ def test_nonzero_walk_correct(shiro, run, knobs):
              ("spmm_t", torch.bfloat16), ("partial_c", torch.float32), ("aggregate_c", torch.float32))
     saved = {k: shiro.get_tuning(run.plan, k[0], run.N, k[1]) for k in kinds}
     for k in kinds:
-        shiro.set_tuning(run.plan, k[0], run.N, k[1], group_rows=2, **knobs)
+        shiro.set_tuning(run.plan, k[0], run.N, k[1], group_rows=walk, **knobs)
     try:
         Bp = shiro.pack_B(run.plan, run.B.to(dev))
         Yref, Yden = _fwd_ref(run, run.B.numpy())
@@ -451,6 +453,62 @@ def test_graph_replays_match_eager(shiro):
     Ac = oracle.Csr.from_synth(A)
     ruc, roff, rcm = oracle.select(Ac)
     assert np.array_equal(uc.cpu().numpy(), ruc) and np.array_equal(cm.cpu().numpy(), rcm)
+
+
+def test_graph_survives_buffer_growth(shiro):
+    """A graph captured at N = 32 keeps its carry and scratch buffers when a
+    later eager call at N = 256 (and a new tuning with smaller chunks) needs
+    larger ones: its replays still match the eager N = 32 result bit for
+    bit, and the eager N = 256 call matches the oracle."""
+    A, _ = make_case("rmat12_P8_p0")
+    dev = torch.device("cuda")
+    Ad = A.to(dev)
+    plan = shiro.partition(Ad.row_ptr, Ad.col, A.n_rows, A.n_cols, A.P, A.p)
+    U, _ = shiro.select_rows(plan)
+    rows = plan.info()["rows"]
+    shiro.prepare(plan, 32, torch.float32, ops=("spmm", "backward"))
+    B32 = synth.dense(A.n_cols, 32, 0, synth.STREAM_B).to(dev)
+    G32 = synth.dense(rows, 32, 0, synth.STREAM_DY).to(dev)
+    Bp = torch.empty(U, 32, device=dev)
+    Y = torch.empty(rows, 32, device=dev)
+    dBp = torch.empty(U, 32, device=dev)
+
+    def step():
+        shiro.refresh_selection(plan)
+        shiro.pack_B(plan, B32, out=Bp)
+        shiro.spmm(plan, Ad.vals, Bp, out=Y)
+        shiro.spmm_backward(plan, Ad.vals, G32, Bp, dBpacked=dBp)
+
+    step()
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in (Bp, Y, dBp)]
+    cs = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with plan.capture(cs) as holder:
+        step()
+    gid = holder[0]
+    # eager calls that grow the carry buffer (wider N, then smaller chunks)
+    B256 = synth.dense(A.n_cols, 256, 0, synth.STREAM_B).to(dev)
+    Bp256 = shiro.pack_B(plan, B256)
+    Y256 = shiro.spmm(plan, Ad.vals, Bp256)
+    shiro.set_tuning(plan, "spmm", 256, chunk=16)
+    Y256b = shiro.spmm(plan, Ad.vals, Bp256)
+    torch.cuda.synchronize()
+    Ac = oracle.Csr.from_synth(A)
+    Bh = B256.cpu().numpy()
+    ref256, den256 = oracle.spmm(Ac, Bh, None), oracle.spmm(Ac, Bh, None, abs_mode=True)
+    assert oracle.rel_err(Y256.cpu().numpy(), ref256, den256) <= TOL_F32
+    assert oracle.rel_err(Y256b.cpu().numpy(), ref256, den256) <= TOL_F32
+    for i in range(3):
+        for t in (Bp, Y, dBp):
+            t.fill_(float("nan"))
+        torch.cuda.synchronize()
+        plan.replay(gid, stream=cs)
+        cs.synchronize()
+        for a, b in zip((Bp, Y, dBp), ref):
+            assert torch.equal(a, b), f"replay {i}"
+        _ = shiro.spmm(plan, Ad.vals, Bp256)  # eager work on the grown buffers between replays
+        torch.cuda.synchronize()
 
 
 def test_autograd_function(shiro):
@@ -766,5 +824,54 @@ def test_error_paths_on_device(shiro):
         shiro.set_tuning(plan, "sddmm", 4, group_rows=2)
     assert e.value.name == "INVALID_ARG"
     with pytest.raises(shiro.ShiroError) as e:
-        shiro.set_tuning(plan, "spmm_t", 4, group_rows=3)
+        shiro.set_tuning(plan, "sddmm", 4, group_rows=3)
     assert e.value.name == "INVALID_ARG"
+    with pytest.raises(shiro.ShiroError) as e:
+        shiro.set_tuning(plan, "spmm_t", 4, group_rows=4)
+    assert e.value.name == "INVALID_ARG"
+
+
+def test_binding_rejects_bad_operands(shiro):
+    """The binding checks device, dtype and shape of every tensor against the
+    plan before a pointer reaches the library: undersized or host tensors
+    raise, and the outputs are left untouched (nothing was launched)."""
+    A, N = make_case("rmat12_P8_p0")
+    dev = torch.device("cuda")
+    Ad = A.to(dev)
+    plan = shiro.partition(Ad.row_ptr, Ad.col, A.n_rows, A.n_cols, A.P, A.p)
+    U, _ = shiro.select_rows(plan)
+    inf = plan.info()
+    rows, ext = inf["rows"], inf["nz_begin"] + inf["nnz"]
+    B = synth.dense(A.n_cols, N, 0, synth.STREAM_B).to(dev)
+    Bp = shiro.pack_B(plan, B)
+    G = synth.dense(rows, N, 0, synth.STREAM_DY).to(dev)
+    sentinel = 3.0
+    Y = torch.full((rows, N), sentinel, device=dev)
+    bad = [
+        lambda: shiro.pack_B(plan, B[: A.n_cols - 1]),                      # B short of n_cols rows
+        lambda: shiro.pack_B(plan, B, out=torch.empty(U - 1, N, device=dev)),  # Bpacked short of U rows
+        lambda: shiro.spmm(plan, Ad.vals[: ext - 1], Bp, out=Y),             # vals short of the panel
+        lambda: shiro.spmm(plan, Ad.vals.cpu(), Bp, out=Y),                  # vals on the host
+        lambda: shiro.spmm(plan, Ad.vals.double(), Bp, out=Y),               # vals not float32
+        lambda: shiro.spmm(plan, Ad.vals, Bp[: U - 1], out=Y),               # Bpacked short of U rows
+        lambda: shiro.spmm(plan, Ad.vals, Bp, out=Y[: rows - 1]),            # Y short of the panel rows
+        lambda: shiro.spmm(plan, Ad.vals, Bp, out=Y.cpu()),                  # Y on the host
+        lambda: shiro.spmm(plan, Ad.vals, Bp, out=torch.empty(rows, N + 1, device=dev)),
+        lambda: shiro.spmm_backward(plan, Ad.vals, G[: rows - 1], Bp, dB=torch.zeros(A.n_cols, N, device=dev)),
+        lambda: shiro.spmm_backward(plan, Ad.vals, G, Bp, dB=torch.zeros(A.n_cols - 1, N, device=dev)),
+        lambda: shiro.spmm_backward(plan, Ad.vals, G, Bp, dBpacked=torch.zeros(U - 1, N, device=dev)),
+        lambda: shiro.spmm_backward(plan, Ad.vals, G, Bp, dvals=torch.zeros(ext - 1, device=dev)),
+        lambda: shiro.spmm_backward(plan, Ad.vals, G, Bp, dvals=torch.zeros(ext, device="cpu")),
+        lambda: shiro.spmm_backward(plan, Ad.vals, G, None, dvals=torch.zeros(ext, device=dev)),
+        lambda: shiro.spmm_backward(plan, Ad.vals, G, Bp.to(torch.bfloat16), dB=torch.zeros(A.n_cols, N, device=dev)),
+    ]
+    for i, f in enumerate(bad):
+        with pytest.raises((ValueError, TypeError)):
+            f()
+        torch.cuda.synchronize()
+        assert bool((Y == sentinel).all()), f"case {i} wrote Y"
+    # the same calls with correct operands still work
+    shiro.spmm(plan, Ad.vals, Bp, out=Y)
+    Ac = oracle.Csr.from_synth(A)
+    Bh = B.cpu().numpy()
+    assert oracle.rel_err(Y.cpu().numpy(), oracle.spmm(Ac, Bh, None), oracle.spmm(Ac, Bh, None, abs_mode=True)) <= TOL_F32

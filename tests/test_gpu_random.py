@@ -111,7 +111,7 @@ def random_tuning(rng, walk=True):
     return dict(chunk=int(rng.choice([16, 48, 100, 128, 512, 2048])),
                 lanes=int(rng.choice([8, 16, 32, 64])),
                 unroll=int(rng.choice([1, 2, 4])),
-                group_rows=int(rng.integers(0, 3 if walk else 2)),
+                group_rows=int(rng.integers(0, 4 if walk else 2)),
                 xcd_remap=int(rng.integers(0, 2)),
                 wg_per_cu=int(rng.choice([1, 2, 4, 8, 16])))
 
