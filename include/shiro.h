@@ -96,7 +96,8 @@ enum {
   SHIRO_ERR_HIP = -4,           /* a HIP runtime call failed                    */
   SHIRO_ERR_UNSUPPORTED = -5,   /* dtype pair or size outside what is built     */
   SHIRO_ERR_NOT_READY = -6,     /* call out of order (e.g. pack before select)  */
-  SHIRO_ERR_CAPTURING = -7      /* would allocate/synchronise during capture    */
+  SHIRO_ERR_CAPTURING = -7,     /* would allocate/synchronise during capture    */
+  SHIRO_ERR_WORKSPACE = -8      /* fixed work area of an allocation-free call too small */
 };
 
 /* shiro_partition flags */
@@ -271,6 +272,26 @@ SHIRO_API int shiro_spmm_backward(shiro_plan plan, const float* d_vals, const vo
                                   shiro_dtype dt, void* d_dBpacked, int64_t lddbp, void* d_dB,
                                   int64_t lddb, float* d_dvals, uint32_t flags,
                                   shiro_stream_t stream);
+
+/* Allocation-free form of shiro_spmm in SHIRO_MODE_BATCHED, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, result
+ * and kernels as shiro_spmm(..., SHIRO_MODE_BATCHED, ...), bit for bit; the
+ * carry slots of rows cut by chunk boundaries live in a fixed 32 MiB device
+ * array of the library (one per device, held until the process ends) instead
+ * of the plan's buffer.  Makes no device or host allocation and does not
+ * synchronise.  The plan must have been prepared for (N, in_dt) with
+ * SHIRO_OP_SPMM under the tuning in force (NOT_READY otherwise); patterns
+ * whose slots (2 * N floats per merge-path chunk) exceed the array return
+ * SHIRO_ERR_WORKSPACE without launching anything.  Must be called with the
+ * plan's device current (INVALID_ARG otherwise).  Every call on one device
+ * shares that device's array and every slot a call reads it first writes, so
+ * nothing needs clearing between calls; calls that overlap in time on one
+ * device (different streams, or threads) race on the array and must be
+ * ordered by the caller. */
+SHIRO_API int shiro_spmm_noalloc(shiro_plan plan, const float* d_vals, const void* d_Bpacked,
+                                 int64_t ldp, int32_t N, shiro_dtype in_dt, void* d_Y, int64_t ldy,
+                                 shiro_dtype out_dt, shiro_stream_t stream);
 
 /* ---- Row-based scheme (Table 1 Rows; Sec. 3.1 row-based scheme, Eq. V_row;
  * Sec. 5.1 stage 3 remote computation, stage 5 aggregation) -------------

@@ -28,6 +28,7 @@ __all__ = [
     "pack_B",
     "spmm",
     "spmm_backward",
+    "spmm_noalloc",
     "select_c_rows",
     "c_row_selection",
     "partial_c",
@@ -324,6 +325,25 @@ def spmm(plan: Plan, vals: torch.Tensor, Bpacked: torch.Tensor, out: Optional[to
     m = {"batched": _lib.MODE_BATCHED, "per_block": _lib.MODE_PER_BLOCK}[mode]
     _lib.check(_L().shiro_spmm(plan.handle, _ptr(vals), _ptr(Bpacked), _ld(Bpacked), N, _dt(Bpacked.dtype),
                                _ptr(out), _ld(out), _dt(out.dtype), m, ctypes.c_void_p(_stream(stream))))
+    return out
+
+
+def spmm_noalloc(plan: Plan, vals: torch.Tensor, Bpacked: torch.Tensor, out: torch.Tensor,
+                 stream=None) -> torch.Tensor:
+    """The batched spmm into a caller-given `out` through the library's
+    allocation-free entry point (fixed device work area; the plan must be
+    prepared for (N, dtype) first).  Same result as spmm, bit for bit."""
+    inf = plan.info()
+    _dev(Bpacked)
+    if Bpacked.dim() != 2:
+        raise ValueError("Bpacked must be 2-D")
+    N = Bpacked.shape[1]
+    _mat(Bpacked, "Bpacked", max(inf["U"], 0), N, tuple(_DT))
+    _vec(vals, "vals", plan.value_extent)
+    _mat(out, "out", inf["rows"], N, tuple(_DT))
+    _lib.check(_L().shiro_spmm_noalloc(plan.handle, _ptr(vals), _ptr(Bpacked), _ld(Bpacked), N,
+                                       _dt(Bpacked.dtype), _ptr(out), _ld(out), _dt(out.dtype),
+                                       ctypes.c_void_p(_stream(stream))))
     return out
 
 

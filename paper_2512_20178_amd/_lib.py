@@ -24,6 +24,7 @@ ERRORS = {
     -5: "UNSUPPORTED",
     -6: "NOT_READY",
     -7: "CAPTURING",
+    -8: "WORKSPACE",
 }
 
 F32 = 0
@@ -77,6 +78,7 @@ EXPORTS = [
     "shiro_graph_launch",
     "shiro_set_allocator",
     "shiro_plan_destroy",
+    "shiro_spmm_noalloc",
 ]
 
 # shiro_alloc_fn / shiro_free_fn
@@ -169,6 +171,7 @@ def load(path: str = LIB_PATH):
         L.shiro_graph_launch.argtypes = [_p, _i32, _p]
         L.shiro_set_allocator.argtypes = [ALLOC_FN, FREE_FN, _p]
         L.shiro_plan_destroy.argtypes = [_p]
+        L.shiro_spmm_noalloc.argtypes = [_p, _p, _p, _i64, _i32, ctypes.c_int, _p, _i64, ctypes.c_int, _p]
         for name in EXPORTS:
             if name != "shiro_last_error":
                 getattr(L, name).restype = ctypes.c_int

@@ -235,7 +235,7 @@ int validate_tuning(int kernel, int32_t, shiro_dtype, const shiro_tuning_t& t) {
   return SHIRO_OK;
 }
 
-static shiro_tuning_t tuning_for(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt) {
+shiro_tuning_t tuning_for(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt) {
   auto it = plan->tuning.find(TuneKey{kernel, N, (int)dt});
   if (it != plan->tuning.end()) return it->second;
   return default_tuning(kernel, N, dt);

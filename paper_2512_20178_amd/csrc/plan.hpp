@@ -223,6 +223,13 @@ int launch_pack(shiro_plan plan, const void* B, int64_t ldb, int32_t N, shiro_dt
 int launch_spmm(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* X,
                 int64_t ldx, int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy,
                 shiro_dtype out_dt, hipStream_t s);
+// The batched product with its carry slots in a caller-given device area of
+// carry_cap floats instead of the plan's buffer; allocates nothing: NOT_READY
+// when the plan lacks the tuning's work list or row ids, WORKSPACE when the
+// slots do not fit.
+int launch_spmm_fixed(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* X,
+                      int64_t ldx, int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy, shiro_dtype out_dt,
+                      float* carry, int64_t carry_cap, hipStream_t s);
 int launch_spmm_per_block(shiro_plan plan, const float* vals, const void* X, int64_t ldx,
                           int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy, shiro_dtype out_dt,
                           hipStream_t s);
@@ -248,6 +255,8 @@ int ensure_acc32(shiro_plan plan, int64_t elems, bool allocate);
 int ensure_tvals(shiro_plan plan, bool allocate);
 
 shiro_tuning_t default_tuning(int kernel, int32_t N, shiro_dtype dt);
+// The tuning a plan uses for one kernel family (its own, else the default).
+shiro_tuning_t tuning_for(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt);
 int validate_tuning(int kernel, int32_t N, shiro_dtype dt, const shiro_tuning_t& t);
 
 }  // namespace shiro

@@ -1618,7 +1618,8 @@ namespace {
 int launch_pattern(shiro_plan plan, const shiro_tuning_t& t, const WorkList* wl, const int64_t* ptr,
                    const int32_t* idx, const float* vals, int64_t R, const void* X, int64_t ldx,
                    int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy, shiro_dtype out_dt,
-                   hipStream_t s, const int32_t* add_rows = nullptr, const int32_t* rid = nullptr) {
+                   hipStream_t s, const int32_t* add_rows = nullptr, const int32_t* rid = nullptr,
+                   float* carry = nullptr) {
   SpmmArgs a{};
   a.ptr = ptr;
   a.rid = rid;
@@ -1637,7 +1638,7 @@ int launch_pattern(shiro_plan plan, const shiro_tuning_t& t, const WorkList* wl,
   }
   a.chunk_row = wl->chunk_row;
   a.chunk_nz = wl->chunk_nz;
-  a.carry = plan->carry;
+  a.carry = carry ? carry : plan->carry;
   a.W = wl->W;
   a.R = (int32_t)R;
   a.N = N;
@@ -1689,6 +1690,26 @@ int launch_spmm(shiro_plan plan, const shiro_tuning_t& t, const float* vals, con
   SHIRO_LAUNCH_CHECK();
   return launch_pattern(plan, t, wl, plan->row_ptr, plan->colmap, v, plan->rows, X, ldx, N, in_dt, Y, ldy,
                         out_dt, s, nullptr, t.group_rows >= 2 ? plan->row_rid : nullptr);
+}
+
+int launch_spmm_fixed(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* X,
+                      int64_t ldx, int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy, shiro_dtype out_dt,
+                      float* carry, int64_t carry_cap, hipStream_t s) {
+  if (plan->rows == 0 || N == 0) return SHIRO_OK;
+  auto it = plan->rows_work.find(t.chunk);
+  if (it == plan->rows_work.end() || (t.group_rows >= 2 && !plan->row_rid))
+    return set_error(SHIRO_ERR_NOT_READY,
+                     "spmm_noalloc: work list of the tuning not built; run shiro_prepare for (N, dtype) first");
+  const WorkList* wl = &it->second;
+  const int64_t need = (int64_t)wl->W * 2 * N;
+  if (need > carry_cap)
+    return set_error(SHIRO_ERR_WORKSPACE,
+                     "spmm_noalloc: the carry slots need " + std::to_string(need * 4) +
+                         " bytes, more than the fixed work area of " + std::to_string(carry_cap * 4) + " bytes");
+  const float* v = plan_values(plan, vals, s);
+  SHIRO_LAUNCH_CHECK();
+  return launch_pattern(plan, t, wl, plan->row_ptr, plan->colmap, v, plan->rows, X, ldx, N, in_dt, Y, ldy,
+                        out_dt, s, nullptr, t.group_rows >= 2 ? plan->row_rid : nullptr, carry);
 }
 
 int build_rowbased(shiro_plan plan, hipStream_t s) {

@@ -187,6 +187,8 @@ def test_binding_rejects_host_operands_before_any_call():
     with pytest.raises(ValueError, match="on the GPU"):
         shiro.spmm(plan, vals, torch.zeros(5, 4))
     with pytest.raises(ValueError, match="on the GPU"):
+        shiro.spmm_noalloc(plan, vals, torch.zeros(5, 4), torch.zeros(8, 4))
+    with pytest.raises(ValueError, match="on the GPU"):
         shiro.spmm_backward(plan, vals, torch.zeros(8, 4), torch.zeros(5, 4), dB=torch.zeros(8, 4))
     with pytest.raises(ValueError, match="on the GPU"):
         shiro.partial_c(plan, vals, B, 3)

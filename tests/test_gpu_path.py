@@ -857,6 +857,7 @@ def test_binding_rejects_bad_operands(shiro):
         lambda: shiro.spmm(plan, Ad.vals, Bp, out=Y[: rows - 1]),            # Y short of the panel rows
         lambda: shiro.spmm(plan, Ad.vals, Bp, out=Y.cpu()),                  # Y on the host
         lambda: shiro.spmm(plan, Ad.vals, Bp, out=torch.empty(rows, N + 1, device=dev)),
+        lambda: shiro.spmm_noalloc(plan, Ad.vals, Bp, Y[: rows - 1]),
         lambda: shiro.spmm_backward(plan, Ad.vals, G[: rows - 1], Bp, dB=torch.zeros(A.n_cols, N, device=dev)),
         lambda: shiro.spmm_backward(plan, Ad.vals, G, Bp, dB=torch.zeros(A.n_cols - 1, N, device=dev)),
         lambda: shiro.spmm_backward(plan, Ad.vals, G, Bp, dBpacked=torch.zeros(U - 1, N, device=dev)),
