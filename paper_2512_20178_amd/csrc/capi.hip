@@ -258,7 +258,9 @@ static void plan_free(shiro_plan plan) {
   dev_free(plan->col);
   dev_free(plan->vmap);
   dev_free(plan->svals);
-  dev_free(plan->flags);
+  dev_free(plan->bits);
+  dev_free(plan->bcol);
+  dev_free(plan->mark_items);
   dev_free(plan->wtab);
   dev_free(plan->unique_cols);
   dev_free(plan->block_off);
@@ -291,6 +293,14 @@ static void plan_free(shiro_plan plan) {
   dev_free(plan->rb.iota);
   dev_free(plan->rb.vals);
   dev_free(plan->rb.block_off);
+  dev_free(plan->pb.ptr);
+  dev_free(plan->pb.idx);
+  dev_free(plan->pb.rid);
+  for (auto& wl : plan->pb.work) {
+    dev_free(wl.chunk_row);
+    dev_free(wl.chunk_nz);
+    dev_free(wl.split);
+  }
   dev_free(plan->carry);
   dev_free(plan->acc32);
   dev_free(plan->scratch);
@@ -591,7 +601,7 @@ static int partition_impl(int64_t n_rows, int64_t n_cols, int64_t nnz, const int
   }
   if ((!d_keep && ((rc = dev_alloc_n(&plan->row_ptr, plan->rows + 1)) ||
                    (rc = dev_alloc_n(&plan->col, std::max<int64_t>(plan->nnz, 1))))) ||
-      (rc = dev_alloc_n(&plan->flags, plan->n_words * 32)) ||
+      (rc = dev_alloc_n(&plan->bits, plan->n_words)) ||
       (rc = dev_alloc_n(&plan->wtab, 2 * plan->n_words)) ||
       (rc = dev_alloc_n(&plan->unique_cols, std::max<int64_t>(std::min(plan->nnz, n_cols), 1))) ||
       (rc = dev_alloc_n(&plan->block_off, (int64_t)P + 1)) ||
@@ -603,8 +613,8 @@ static int partition_impl(int64_t n_rows, int64_t n_cols, int64_t nnz, const int
         hipMemcpyAsync(plan->col, d_col + nz0, (size_t)plan->nnz * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
       return fail(set_error(SHIRO_ERR_HIP, "partition: copying the panel's columns failed"));
   }
-  // the selection expects all-zero flags (each selection clears what it set)
-  if ((rc = launch_zero_bytes(plan->flags, plan->n_words * 32, s))) return fail(rc);
+  // the selection expects an all-zero bitmap (each selection clears what it set)
+  if ((rc = launch_zero_bytes(reinterpret_cast<uint8_t*>(plan->bits), plan->n_words * 4, s))) return fail(rc);
 
   if ((flags & SHIRO_CHECK_CSR) || env_check()) {
     if ((rc = ensure_scratch(plan, 256))) return fail(rc);
@@ -898,7 +908,9 @@ SHIRO_API int shiro_prepare(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t
     }
   }
   if (ops & SHIRO_OP_PER_BLOCK) {
-    SHIRO_TRY(build_segments(plan, s));
+    if (plan->vmap) return set_error(SHIRO_ERR_UNSUPPORTED, "prepare: per-block mode is not available on subset plans");
+    SHIRO_TRY(build_per_block(plan, s));
+    SHIRO_TRY(ensure_carry(plan, (int64_t)plan->pb.max_W * 2 * N, true));
     if (dt == SHIRO_BF16) SHIRO_TRY(ensure_acc32(plan, plan->rows * (int64_t)N, true));
   }
   SHIRO_HIP(hipStreamSynchronize(s));

@@ -69,6 +69,19 @@ struct RowBased {
   int64_t* block_off = nullptr; // P + 1: first entry of each block
 };
 
+// One launch per column block (the baseline of the batched form): each
+// block's own CSR over its (row, block) entries, in the row-based scheme's
+// block-major order, with a work list per block.
+struct PerBlock {
+  bool built = false;
+  int64_t* ptr = nullptr;        // R + P: block q's rebased row pointer at off[q] + q
+  int32_t* idx = nullptr;        // nnz: packed row of each block-major nonzero
+  int32_t* rid = nullptr;        // nnz: entry of each nonzero, counted from its block's first entry
+  std::vector<WorkList> work;    // P
+  std::vector<int64_t> nz_off;   // P + 1: first block-major nonzero of each block
+  int32_t max_W = 0;
+};
+
 struct TuneKey {
   int kernel, N, dt;
   bool operator<(const TuneKey& o) const {
@@ -99,7 +112,12 @@ struct shiro_plan_s {
   bool selected = false;
   int64_t U = -1;
   int64_t n_words = 0;
-  uint8_t* flags = nullptr;     // 32 * n_words: 1 if the column id occurs in the panel
+  uint32_t* bits = nullptr;     // n_words: bit c set if column id c occurs in the panel
+                                // (all zero between selections)
+  int32_t* bcol = nullptr;      // nnz: the panel's column ids grouped by bins of 2^17 ids
+  int32_t* mark_items = nullptr;  // 3 per chunk of bcol: bin, first, end
+  int32_t n_mark_items = 0;
+  bool bins_built = false;
   uint32_t* wtab = nullptr;     // 2 * n_words: (bits, exclusive prefix of popcounts) per word
   int32_t* unique_cols = nullptr;  // capacity min(nnz, n_cols)
   int64_t* block_off = nullptr;    // P + 1
@@ -113,6 +131,7 @@ struct shiro_plan_s {
   shiro::Transposed tr;
   shiro::BlockSegments seg;
   shiro::RowBased rb;
+  shiro::PerBlock pb;
   std::map<int32_t, shiro::WorkList> rb_work;   // keyed by chunk size (partial C rows)
   std::map<int32_t, shiro::WorkList> agg_work;  // keyed by chunk size (sum into the panel)
 
@@ -190,6 +209,7 @@ int build_worklist(const int64_t* ptr, int64_t R, int64_t nnz, int32_t chunk, Wo
 int build_transposed(shiro_plan plan, hipStream_t s);
 int build_segments(shiro_plan plan, hipStream_t s);
 int build_rowbased(shiro_plan plan, hipStream_t s);
+int build_per_block(shiro_plan plan, hipStream_t s);
 // The panel rows' ids per nonzero (plan->row_rid), built once.
 int ensure_row_rid(shiro_plan plan, bool allocate, hipStream_t s);
 // Joint row-column strategy (host): minimum weighted vertex cover of one

@@ -1,14 +1,23 @@
 // Panel extraction and Cols(A^(p,q)) selection.
 //
 // Selection (Table 1; Sec. 3.1 column-based scheme; Sec. 5.1 stage 1) runs
-// over the whole panel at once: one flag byte per global column id marks the
-// columns present in the panel (plain byte stores of 1: idempotent, no
-// atomics, so they stay in each XCD's L2 and merge by byte mask on
-// write-back), the flags are folded into one bit per id, a prefix sum of the
-// per-word popcounts gives every present column its packed position, and
-// because column blocks are contiguous id ranges the positions are already
-// grouped block by block in ascending id order.  block_off[q] is the rank of
-// block q's first column id.
+// over the whole panel at once, on a bitmap of the panel's column ids: one
+// bit per global id, set for the ids present in the panel.  A prefix sum of
+// the per-word popcounts gives every present column its packed position,
+// and because column blocks are contiguous id ranges the positions are
+// already grouped block by block in ascending id order; block_off[q] is the
+// rank of block q's first column id.
+//
+// The bitmap is built from a copy of the panel's column ids grouped by bins
+// of 2^17 ids (made once, at the first selection: a stable radix sort on the
+// bin).  A workgroup takes a chunk of one bin, sets the bits of its ids in a
+// 16 KB bitmap in LDS (integer OR: the result does not depend on the order)
+// and ORs the non-zero words into the global bitmap, so nothing is written
+// at random into global memory.  The scan's down pass writes the word table
+// used by the remap and clears the bitmap for the next selection.
+#include <algorithm>
+#include <vector>
+
 #include "plan.hpp"
 #include "scan.hpp"
 
@@ -85,24 +94,7 @@ __global__ void k_block_nnz_global(const int32_t* __restrict__ col, int64_t nnz,
     atomicAdd(&out[(int64_t)col[k] / K], 1ull);
 }
 
-// flag[c] = 1 for every column id c of the panel.  Four ids per thread
-// (one 16-byte load when the panel's col array allows it).
-__global__ void k_mark(const int32_t* __restrict__ col, int64_t nnz, uint8_t* __restrict__ flag) {
-  const int64_t n4 = ((uintptr_t)col % 16 == 0) ? (nnz >> 2) : 0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const u32x4 c = reinterpret_cast<const u32x4*>(col)[i];
-    flag[c.x] = 1;
-    flag[c.y] = 1;
-    flag[c.z] = 1;
-    flag[c.w] = 1;
-  }
-  for (int64_t k = (n4 << 2) + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz;
-       k += (int64_t)gridDim.x * blockDim.x)
-    flag[col[k]] = 1;
-}
-
-// Zero the flag bytes (16 bytes per store; the tail byte by byte).
+// Zero a byte range (16 bytes per store; the tail byte by byte).
 __global__ void k_zero_bytes(uint8_t* __restrict__ p, int64_t n) {
   const int64_t n16 = n >> 4;
   u32x4 z = {0u, 0u, 0u, 0u};
@@ -114,110 +106,105 @@ __global__ void k_zero_bytes(uint8_t* __restrict__ p, int64_t n) {
     p[i] = 0;
 }
 
-// Word table: wtab[2 w] = bits of word w (bit b = flag[32 w + b]; the flag
-// array is padded to whole words), wtab[2 w + 1] = packed position of the
-// word's first set bit.  Interleaved so that the remap reads one 8-byte entry.
-// The flags read are cleared again (only the 16-byte pieces that held a 1),
-// so the array is all zero between selections; it is cleared once when the
-// plan is made.
-__global__ void k_fold_flags(uint8_t* __restrict__ flag, int64_t n_words,
-                             uint32_t* __restrict__ wtab) {
-  const u32x4 zero = {0u, 0u, 0u, 0u};
-  for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < n_words;
-       w += (int64_t)gridDim.x * blockDim.x) {
-    u32x4* f = reinterpret_cast<u32x4*>(flag + (w << 5));
-    const u32x4 a = f[0], b = f[1];
-    if ((a.x | a.y | a.z | a.w) != 0u) f[0] = zero;
-    if ((b.x | b.y | b.z | b.w) != 0u) f[1] = zero;
-    const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-    uint32_t m = 0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      // each byte is 0 or 1: gather bit 0 of the four bytes of v[i]
-      const uint32_t x = v[i];
-      const uint32_t q = (x & 1u) | ((x >> 7) & 2u) | ((x >> 14) & 4u) | ((x >> 21) & 8u);
-      m |= q << (4 * i);
+constexpr int kBinShift = 17;                          // column ids per bin: 2^17
+constexpr int kBinWords = 1 << (kBinShift - 5);        // 4096 bitmap words (16 KB)
+
+// Bin of each column id (the sort key of the bin-major copy).
+__global__ void k_bin_keys(const int32_t* __restrict__ col, int64_t nnz, uint32_t* __restrict__ key) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * blockDim.x)
+    key[k] = (uint32_t)col[k] >> kBinShift;
+}
+
+// off[b] = first entry of bin b in the sorted keys (lower bound), off[nbins] = n.
+__global__ void k_bin_off(const uint32_t* __restrict__ skey, int64_t n, int64_t nbins, int64_t* __restrict__ off) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b <= nbins;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if ((int64_t)skey[mid] < b) lo = mid + 1; else hi = mid;
     }
-    wtab[2 * w] = m;
+    off[b] = lo;
+  }
+}
+
+// One chunk (bin, begin, end) of the bin-major ids per workgroup: the bits
+// of its ids in an LDS bitmap of the bin, then the non-zero words ORed into
+// the panel's bitmap.
+__global__ __launch_bounds__(kBlock) void k_mark_bins(const int32_t* __restrict__ bcol,
+                                                      const int32_t* __restrict__ items,
+                                                      uint32_t* __restrict__ bits, int64_t n_words) {
+  __shared__ uint32_t lb[kBinWords];
+  for (int i = threadIdx.x; i < kBinWords; i += kBlock) lb[i] = 0;
+  __syncthreads();
+  const int32_t bin = items[3 * blockIdx.x];
+  const int64_t b = items[3 * blockIdx.x + 1], e = items[3 * blockIdx.x + 2];
+  // four ids in flight per thread
+  for (int64_t k0 = b + threadIdx.x; k0 < e; k0 += 4 * kBlock) {
+    uint32_t c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = k0 + u * kBlock;
+      c[u] = (uint32_t)bcol[k < e ? k : e - 1];  // a repeated id sets a bit already set
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) atomicOr(&lb[(c[u] >> 5) & (kBinWords - 1)], 1u << (c[u] & 31u));
+  }
+  __syncthreads();
+  const int64_t w0 = (int64_t)bin * kBinWords;
+  for (int i = threadIdx.x; i < kBinWords; i += kBlock) {
+    const uint32_t v = lb[i];
+    if (v != 0u && w0 + i < n_words) atomicOr(&bits[w0 + i], v);
   }
 }
 
 struct PopcountIn {
-  const uint32_t* wtab;
-  __device__ int64_t operator()(int64_t w) const { return __popc(wtab[2 * w]); }
+  const uint32_t* bits;
+  __device__ int64_t operator()(int64_t w) const { return __popc(bits[w]); }
 };
 
-// Down pass of the selection scan.  A workgroup owns kSelItems*256 words:
-// it scans their popcounts (plus the tile offset from the tile scan), writes
-// each word's packed offset into the word table, and then compacts the ids
-// of the set bits, so that stores of neighbouring ids are neighbours and no
-// lane walks a dense word alone.  A sparse tile (most of them: 7% of the
-// bits are set on the 2^24 R-MAT panel) is compacted output by output: lane
-// t takes outputs t, t+256, ..., finds the word holding each by binary
-// search over the tile's word offsets in LDS and the bit inside it by
-// popcount halving.  A dense tile is scanned bit by bit, one id per lane.
-constexpr int kSelItems = 4;
+// Down pass of the selection scan: a workgroup owns 512 words (two per
+// thread); it scans their popcounts (plus the tile offset from the tile
+// scan), writes the word table entries (bits, packed position of the word's
+// first set bit) that the remap reads, clears the bitmap words it read, and
+// compacts the ids of the set bits: each lane writes its words' ids into the
+// tile's slice of an LDS buffer, then the workgroup copies the slice to
+// unique_cols with consecutive lanes on consecutive ids.
+constexpr int kSelItems = 2;
 
-// Position of the r-th set bit (r counted from 0) of w; r < popcount(w).
-__device__ __forceinline__ uint32_t select_bit(uint32_t w, uint32_t r) {
-  uint32_t pos = 0;
-#pragma unroll
-  for (int h = 16; h >= 1; h >>= 1) {
-    const uint32_t c = __popc(w & ((1u << h) - 1u));
-    const bool up = r >= c;
-    r = up ? r - c : r;
-    w = up ? w >> h : w;
-    pos += up ? (uint32_t)h : 0u;
-  }
-  return pos;
-}
-
-__global__ __launch_bounds__(kBlock) void k_select_down(uint32_t* __restrict__ wtab, int64_t n_words,
-                                                        const int64_t* __restrict__ tile_off,
+__global__ __launch_bounds__(kBlock) void k_select_down(uint32_t* __restrict__ bits, uint32_t* __restrict__ wtab,
+                                                        int64_t n_words, const int64_t* __restrict__ tile_off,
                                                         int32_t* __restrict__ unique_cols) {
-  constexpr int TW = kBlock * kSelItems;  // words per tile
   __shared__ int64_t lds[kWavesPerBlock];
-  __shared__ uint32_t sbits[TW];
-  __shared__ uint32_t spref[TW];  // offset of each word inside the tile
-  const int64_t tile0 = (int64_t)blockIdx.x * TW;
-  const int64_t base = tile0 + (int64_t)threadIdx.x * kSelItems;
-  const int64_t toff = tile_off[blockIdx.x];
-  uint32_t bits[kSelItems];
-  int64_t s = 0;
+  __shared__ int32_t ids[kBlock * kSelItems * 32];  // at most 32 ids per word
+  const int64_t w0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kSelItems;
+  uint32_t v[kSelItems];
+  int64_t cnt = 0;
 #pragma unroll
   for (int i = 0; i < kSelItems; ++i) {
-    bits[i] = (base + i < n_words) ? wtab[2 * (base + i)] : 0u;
-    s += __popc(bits[i]);
+    v[i] = w0 + i < n_words ? bits[w0 + i] : 0u;
+    cnt += __popc(v[i]);
   }
   int64_t tot;
-  int64_t ex = block_exclusive_scan<int64_t>(s, lds, &tot);
+  int32_t o = (int32_t)block_exclusive_scan<int64_t>(cnt, lds, &tot);
+  const int64_t toff = tile_off[blockIdx.x];
 #pragma unroll
   for (int i = 0; i < kSelItems; ++i) {
-    if (base + i < n_words) wtab[2 * (base + i) + 1] = (uint32_t)(toff + ex);
-    sbits[threadIdx.x * kSelItems + i] = bits[i];
-    spref[threadIdx.x * kSelItems + i] = (uint32_t)ex;
-    ex += __popc(bits[i]);
+    const int64_t w = w0 + i;
+    if (w < n_words) {
+      const u32x2 t = {v[i], (uint32_t)(toff + o)};
+      reinterpret_cast<u32x2*>(wtab)[w] = t;
+      if (v[i] != 0u) bits[w] = 0u;
+    }
+    uint32_t m = v[i];
+    while (m != 0u) {
+      ids[o++] = (int32_t)((w << 5) + __builtin_ctz(m));
+      m &= m - 1u;
+    }
   }
   __syncthreads();
-  const int32_t count = (int32_t)tot;
-  if (count <= TW * 4) {  // sparse: walk the outputs
-    for (int32_t o = threadIdx.x; o < count; o += kBlock) {
-      int32_t lo = 0, hi = TW - 1;  // last word whose offset is <= o
-      while (lo < hi) {
-        const int32_t mid = (lo + hi + 1) >> 1;
-        if ((int32_t)spref[mid] <= o) lo = mid; else hi = mid - 1;
-      }
-      const uint32_t b = select_bit(sbits[lo], (uint32_t)(o - (int32_t)spref[lo]));
-      unique_cols[toff + o] = (int32_t)(((tile0 + lo) << 5) + b);
-    }
-  } else {  // dense: walk the bits
-    for (int32_t j = threadIdx.x; j < TW * 32; j += kBlock) {
-      const int32_t lw = j >> 5;
-      const uint32_t b = (uint32_t)j & 31u;
-      const uint32_t wb = sbits[lw];
-      if ((wb >> b) & 1u) unique_cols[toff + spref[lw] + __popc(wb & ((1u << b) - 1u))] = (int32_t)((tile0 << 5) + j);
-    }
-  }
+  for (int32_t q = threadIdx.x; q < (int32_t)tot; q += kBlock) unique_cols[toff + q] = ids[q];
 }
 
 // colmap[k] = packed position of col[k] = offset of its word + set bits
@@ -241,14 +228,11 @@ __global__ void k_remap(const int32_t* __restrict__ col, int64_t nnz,
   }
   const bool vec = ((uintptr_t)col % 16 == 0) && ((uintptr_t)colmap % 16 == 0);
   const int64_t n4 = vec ? (nnz >> 2) : 0;
+  auto rank = [&](uint32_t c, const u32x2& e) { return e.y + __popc(e.x & ((1u << (c & 31u)) - 1u)); };
   for (int64_t i = t0; i < n4; i += (int64_t)gridDim.x * blockDim.x) {
-    const u32x4 c = reinterpret_cast<const u32x4*>(col)[i];
-    const u32x2 e0 = tab[c.x >> 5], e1 = tab[c.y >> 5], e2 = tab[c.z >> 5], e3 = tab[c.w >> 5];
-    u32x4 o;
-    o.x = e0.y + __popc(e0.x & ((1u << (c.x & 31u)) - 1u));
-    o.y = e1.y + __popc(e1.x & ((1u << (c.y & 31u)) - 1u));
-    o.z = e2.y + __popc(e2.x & ((1u << (c.z & 31u)) - 1u));
-    o.w = e3.y + __popc(e3.x & ((1u << (c.w & 31u)) - 1u));
+    const u32x4 a = reinterpret_cast<const u32x4*>(col)[i];
+    const u32x2 e0 = tab[a.x >> 5], e1 = tab[a.y >> 5], e2 = tab[a.z >> 5], e3 = tab[a.w >> 5];
+    const u32x4 o = {rank(a.x, e0), rank(a.y, e1), rank(a.z, e2), rank(a.w, e3)};
     reinterpret_cast<u32x4*>(colmap)[i] = o;
   }
   for (int64_t k = (n4 << 2) + t0; k < nnz; k += (int64_t)gridDim.x * blockDim.x) {
@@ -366,30 +350,79 @@ int launch_zero_bytes(uint8_t* p, int64_t n, hipStream_t s) {
   return SHIRO_OK;
 }
 
+// The bin-major copy of the panel's column ids and its chunk list (setup,
+// once per plan): a stable radix sort on the bin, then chunks of at most
+// `chunk` ids that never cross a bin.
+static int build_bins(shiro_plan plan, hipStream_t s) {
+  const int64_t nnz = plan->nnz;
+  plan->n_mark_items = 0;
+  if (nnz == 0) {
+    plan->bins_built = true;
+    return SHIRO_OK;
+  }
+  const int64_t nbins = ceil_div(plan->n_cols, (int64_t)1 << kBinShift);
+  auto al = [](int64_t b) { return (b + 255) / 256 * 256; };
+  SHIRO_TRY(ensure_scratch(plan, 2 * al(nnz * 4) + al((nbins + 1) * 8) + sort_scratch_bytes(nnz)));
+  char* p = reinterpret_cast<char*>(plan->scratch);
+  uint32_t* key = reinterpret_cast<uint32_t*>(p);
+  uint32_t* skey = reinterpret_cast<uint32_t*>(p + al(nnz * 4));
+  int64_t* off = reinterpret_cast<int64_t*>(p + 2 * al(nnz * 4));
+  void* tmp = p + 2 * al(nnz * 4) + al((nbins + 1) * 8);
+  SHIRO_TRY(dev_alloc_n(&plan->bcol, nnz));
+  k_bin_keys<<<grid_for(nnz), kBlock, 0, s>>>(plan->col, nnz, key);
+  SHIRO_LAUNCH_CHECK();
+  int bits = 0;
+  while (bits < 32 && ((int64_t)1 << bits) < nbins) ++bits;
+  SHIRO_TRY(radix_sort_pairs(key, reinterpret_cast<const uint32_t*>(plan->col), skey,
+                             reinterpret_cast<uint32_t*>(plan->bcol), nnz, bits, tmp, s));
+  k_bin_off<<<grid_for(nbins + 1), kBlock, 0, s>>>(skey, nnz, nbins, off);
+  SHIRO_LAUNCH_CHECK();
+  std::vector<int64_t> h((size_t)nbins + 1);
+  SHIRO_HIP(hipMemcpyAsync(h.data(), off, (size_t)(nbins + 1) * 8, hipMemcpyDeviceToHost, s));
+  SHIRO_HIP(hipStreamSynchronize(s));
+  // about two chunks per compute unit, 2048 to 65536 ids each
+  const int64_t chunk = std::min<int64_t>(std::max<int64_t>(ceil_div(nnz, 2 * (int64_t)plan->num_cus), 2048), 65536);
+  std::vector<int32_t> items;
+  for (int64_t b = 0; b < nbins; ++b)
+    for (int64_t st = h[b]; st < h[b + 1]; st += chunk) {
+      items.push_back((int32_t)b);
+      items.push_back((int32_t)st);
+      items.push_back((int32_t)std::min(st + chunk, h[b + 1]));
+    }
+  plan->n_mark_items = (int32_t)(items.size() / 3);
+  SHIRO_TRY(dev_alloc_n(&plan->mark_items, std::max<int64_t>((int64_t)items.size(), 3)));
+  if (!items.empty())
+    SHIRO_HIP(hipMemcpy(plan->mark_items, items.data(), items.size() * 4, hipMemcpyHostToDevice));
+  plan->bins_built = true;
+  return SHIRO_OK;
+}
+
 int run_select(shiro_plan plan, hipStream_t s, bool sync) {
   const int64_t nw = plan->n_words;
   const int64_t nnz = plan->nnz;
+  if (!plan->bins_built) {
+    if (!sync) return set_error(SHIRO_ERR_NOT_READY, "select: the bin-major pattern copy is not built");
+    SHIRO_TRY(build_bins(plan, s));
+  }
   // scratch: [U (int64)] [scan tile sums]
   SHIRO_TRY(ensure_scratch(plan, 256 + scan_scratch_bytes(nw)));  // (sized for 1 item per thread)
   int64_t* d_U = reinterpret_cast<int64_t*>(plan->scratch);
   void* scan_tmp = reinterpret_cast<char*>(plan->scratch) + 256;
 
-  // the flag bytes are all zero here: cleared when the plan was made and
-  // by every fold since
-  if (nnz > 0) {
-    k_mark<<<grid_for((nnz + 3) / 4), kBlock, 0, s>>>(plan->col, nnz, plan->flags);
+  // the bitmap is all zero here: cleared when the plan was made and by
+  // every down pass since
+  if (plan->n_mark_items > 0) {
+    k_mark_bins<<<plan->n_mark_items, kBlock, 0, s>>>(plan->bcol, plan->mark_items, plan->bits, nw);
     SHIRO_LAUNCH_CHECK();
   }
-  k_fold_flags<<<grid_for(nw), kBlock, 0, s>>>(plan->flags, nw, plan->wtab);
-  SHIRO_LAUNCH_CHECK();
   // reduce-then-scan over the word popcounts; the down pass compacts the ids
   const int64_t ntiles = scan_tiles_of(nw, kSelItems);
   int64_t* sums = reinterpret_cast<int64_t*>(scan_tmp);
-  k_scan_reduce<kSelItems, PopcountIn><<<dim3((unsigned)ntiles), kBlock, 0, s>>>(PopcountIn{plan->wtab}, nw, sums);
+  k_scan_reduce<kSelItems, PopcountIn><<<dim3((unsigned)ntiles), kBlock, 0, s>>>(PopcountIn{plan->bits}, nw, sums);
   SHIRO_LAUNCH_CHECK();
   k_scan_tiles<<<1, kBlock, 0, s>>>(sums, ntiles, d_U);
   SHIRO_LAUNCH_CHECK();
-  k_select_down<<<dim3((unsigned)ntiles), kBlock, 0, s>>>(plan->wtab, nw, sums, plan->unique_cols);
+  k_select_down<<<dim3((unsigned)ntiles), kBlock, 0, s>>>(plan->bits, plan->wtab, nw, sums, plan->unique_cols);
   SHIRO_LAUNCH_CHECK();
   k_remap<<<grid_for(std::max<int64_t>((nnz + 3) / 4, (int64_t)plan->P + 1)), kBlock, 0, s>>>(
       plan->col, nnz, plan->wtab, plan->colmap, plan->n_cols, plan->K, plan->P, d_U, plan->block_off);

@@ -1025,44 +1025,41 @@ __global__ __launch_bounds__(kBlock) void k_pack(const int32_t* __restrict__ uc,
 }
 
 // ---------------------------------------------------------------------------
-// one launch per column block: Y[row] += segment sum (blocks in order)
+// one launch per column block (the baseline of the batched form)
 // ---------------------------------------------------------------------------
-template <typename TIN, typename TOUT, int LANES, int VEC>
-__global__ __launch_bounds__(kBlock) void k_spmm_segments(
-    const int32_t* __restrict__ seg_row, const int32_t* __restrict__ seg_begin,
-    const int32_t* __restrict__ seg_end, int64_t s0, int64_t s1, const int32_t* __restrict__ colmap,
-    const float* __restrict__ vals, const TIN* __restrict__ X, int64_t ldx, TOUT* __restrict__ Y,
-    int64_t ldy, int32_t N, int first) {
-  constexpr int G = kWave / LANES;
-  constexpr int TW = LANES * VEC;
-  const int lane = lane_id();
-  const int g = lane / LANES;
-  const int li = lane % LANES;
-  const int64_t groups = (int64_t)gridDim.x * kWavesPerBlock * G;
-  for (int64_t s = s0 + ((int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)) * G + g; s < s1;
-       s += groups) {
-    const int32_t r = seg_row[s];
-    const int32_t kb = seg_begin[s], ke = seg_end[s];
-    for (int64_t c = (int64_t)li * VEC; c < N; c += TW) {
-      float acc[VEC];
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
-      for (int32_t k = kb; k < ke; ++k) {
-        float x[VEC];
-        Elem<TIN>::template load<VEC>(X + (int64_t)colmap[k] * ldx + c, x);
-        const float v = vals[k];
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[e] = fmaf(v, x[e], acc[e]);
-      }
-      TOUT* o = Y + (int64_t)r * ldy + c;
-      if (!first) {
-        float cur[VEC];
-        Elem<TOUT>::template load<VEC>(o, cur);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[e] += cur[e];
-      }
-      Elem<TOUT>::template store<VEC>(o, acc);
+// Block q's own CSR over its (row, block) entries, in the block-major order of
+// the row-based structures: x in [off[q] + q, off[q+1] + q] is entry
+// i = x - off[q] - q of block q, and its row pointer is rebased to the
+// block's first nonzero.
+__global__ void k_pb_ptr(const int64_t* __restrict__ rb_ptr, const int64_t* __restrict__ off, int32_t P,
+                         int64_t total, int64_t* __restrict__ pb_ptr) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = P - 1;  // last q with off[q] + q <= x
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (off[mid] + mid <= x) lo = mid; else hi = mid - 1;
     }
+    const int64_t e0 = off[lo];
+    pb_ptr[x] = rb_ptr[e0 + (x - e0 - lo)] - rb_ptr[e0];
+  }
+}
+
+// For block-major nonzero t: its packed row (colmap of its CSR position) and
+// its entry counted from the block's first entry.
+__global__ void k_pb_fill(const int32_t* __restrict__ rb_rid, const int32_t* __restrict__ rb_perm,
+                          const int32_t* __restrict__ colmap, const int64_t* __restrict__ off, int32_t P,
+                          int64_t nnz, int32_t* __restrict__ pb_idx, int32_t* __restrict__ pb_rid) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nnz;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t j = rb_rid[t];
+    int32_t lo = 0, hi = P - 1;  // last q with off[q] <= j
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= j) lo = mid; else hi = mid - 1;
+    }
+    pb_idx[t] = colmap[rb_perm[t]];
+    pb_rid[t] = (int32_t)(j - off[lo]);
   }
 }
 
@@ -1889,56 +1886,110 @@ int launch_sddmm(shiro_plan plan, const shiro_tuning_t& t, const float*, const v
   return sddmm_dispatch<bf16_t, 1>(tt, dim3(nb), s, a);
 }
 
+// Per-block structures (setup): each column block's own CSR over its (row,
+// block) entries, rebased, with a merge-path work list whose chunk size
+// spreads the block over the whole persistent grid of the walk.
+int build_per_block(shiro_plan plan, hipStream_t s) {
+  PerBlock& pb = plan->pb;
+  if (pb.built) return SHIRO_OK;
+  SHIRO_TRY(build_rowbased(plan, s));
+  const RowBased& rb = plan->rb;
+  const int64_t R = rb.R, nnz = plan->nnz;
+  const int32_t P = plan->P;
+  const auto& off = plan->seg.h_off;
+  SHIRO_TRY(dev_alloc_n(&pb.ptr, R + P));
+  SHIRO_TRY(dev_alloc_n(&pb.idx, std::max<int64_t>(nnz, 1)));
+  SHIRO_TRY(dev_alloc_n(&pb.rid, std::max<int64_t>(nnz, 1)));
+  k_pb_ptr<<<grid_for(R + P), kBlock, 0, s>>>(rb.ptr, rb.block_off, P, R + P, pb.ptr);
+  SHIRO_LAUNCH_CHECK();
+  if (nnz > 0) {
+    k_pb_fill<<<grid_for(nnz), kBlock, 0, s>>>(rb.rid, rb.perm, plan->colmap, rb.block_off, P, nnz, pb.idx, pb.rid);
+    SHIRO_LAUNCH_CHECK();
+  }
+  std::vector<int64_t> h_ptr((size_t)R + 1);
+  SHIRO_HIP(hipMemcpyAsync(h_ptr.data(), rb.ptr, (size_t)(R + 1) * 8, hipMemcpyDeviceToHost, s));
+  SHIRO_HIP(hipStreamSynchronize(s));
+  const shiro_tuning_t t = tuning_for(plan, SHIRO_KERNEL_SPMM, 128, SHIRO_F32);
+  const int64_t workers = (int64_t)plan->num_cus * t.wg_per_cu * kWavesPerBlock * 2;
+  pb.work.assign((size_t)P, WorkList{});
+  for (int32_t q = 0; q < P; ++q) {
+    const int64_t Rq = off[q + 1] - off[q];
+    const int64_t nq = h_ptr[off[q + 1]] - h_ptr[off[q]];
+    if (nq == 0) continue;
+    const int32_t chunk = (int32_t)std::min<int64_t>(std::max<int64_t>(ceil_div(Rq + nq, workers), 16), 4096);
+    SHIRO_TRY(build_worklist(pb.ptr + off[q] + q, Rq, nq, chunk, &pb.work[q], s));
+    pb.max_W = std::max(pb.max_W, pb.work[q].W);
+  }
+  pb.nz_off.assign((size_t)P + 1, 0);
+  for (int32_t q = 0; q <= P; ++q) pb.nz_off[q] = h_ptr[off[q]];
+  pb.built = true;
+  return SHIRO_OK;
+}
+
+// One launch of the tuned walk per column block, each over that block's own
+// work list, adding the block's partial rows into Y in block order (the
+// paper's one local product per block followed by aggregation).  Partial
+// sums go straight into Y when Y is float32, else into a float32 workspace
+// rounded to bfloat16 once at the end.
 int launch_spmm_per_block(shiro_plan plan, const float* vals, const void* X, int64_t ldx,
                           int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy, shiro_dtype out_dt,
                           hipStream_t s) {
   if (plan->vmap) return set_error(SHIRO_ERR_UNSUPPORTED, "per-block mode is not available on subset plans");
   if (plan->rows == 0 || N == 0) return SHIRO_OK;
-  if (!plan->seg.built) {
-    if (stream_capturing(s))
-      return set_error(SHIRO_ERR_CAPTURING, "per-block spmm: segments not prepared before capture");
-    SHIRO_TRY(build_segments(plan, s));
-  }
   if (in_dt == SHIRO_F32 && out_dt != SHIRO_F32)
     return set_error(SHIRO_ERR_UNSUPPORTED, "spmm: dtype pair not supported");
-  const float* v = vals + plan->nz_begin;
-  const auto& off = plan->seg.h_off;
-  // Block partials are summed in float32: straight into Y when Y is float32,
-  // else into a float32 workspace rounded to bfloat16 once at the end.
+  const bool cap = stream_capturing(s);
+  if (!plan->pb.built) {
+    if (cap) return set_error(SHIRO_ERR_CAPTURING, "per-block spmm: block structures not prepared before capture");
+    SHIRO_TRY(build_per_block(plan, s));
+  }
+  const PerBlock& pb = plan->pb;
+  SHIRO_TRY(ensure_carry(plan, (int64_t)pb.max_W * 2 * N, !cap));
   float* acc = reinterpret_cast<float*>(Y);
   int64_t lda = ldy;
   if (out_dt == SHIRO_BF16) {
-    SHIRO_TRY(ensure_acc32(plan, plan->rows * (int64_t)N, !stream_capturing(s)));
+    SHIRO_TRY(ensure_acc32(plan, plan->rows * (int64_t)N, !cap));
     acc = plan->acc32;
     lda = N;
   }
-  auto run = [&](auto tin, auto L, auto V) -> int {
-    using TIN = decltype(tin);
-    k_zero_rows<float><<<grid_for(plan->rows * (int64_t)N, 65536), kBlock, 0, s>>>(acc, plan->rows, lda, N);
+  k_zero_rows<float><<<grid_for(plan->rows * (int64_t)N, 65536), kBlock, 0, s>>>(acc, plan->rows, lda, N);
+  SHIRO_LAUNCH_CHECK();
+  if (plan->nnz > 0) {
+    // values in block-major order (they may change from call to call)
+    k_gather_vals<<<grid_for(plan->nnz), kBlock, 0, s>>>(plan->rb.perm, vals + plan->nz_begin, plan->nnz,
+                                                          plan->rb.vals);
     SHIRO_LAUNCH_CHECK();
-    for (int32_t q = 0; q < plan->P; ++q) {
-      const int64_t s0 = off[q], s1 = off[q + 1];
-      if (s1 <= s0) continue;
-      constexpr int G = kWave / decltype(L)::value;
-      const unsigned nb = grid_for(ceil_div(s1 - s0, G) * kWave, (int64_t)plan->num_cus * 16);
-      k_spmm_segments<TIN, float, decltype(L)::value, decltype(V)::value><<<nb, kBlock, 0, s>>>(
-          plan->seg.seg_row, plan->seg.seg_begin, plan->seg.seg_end, s0, s1, plan->colmap, v,
-          (const TIN*)X, ldx, acc, lda, N, 0);
-      SHIRO_LAUNCH_CHECK();
+  }
+  shiro_tuning_t t = tuning_for(plan, SHIRO_KERNEL_SPMM, N, in_dt);
+  if (t.group_rows < 2) t.group_rows = 2;  // the walk: every block's entries are non-empty rows
+  const auto& off = plan->seg.h_off;
+  for (int32_t q = 0; q < plan->P; ++q) {
+    const WorkList& wl = pb.work[q];
+    if (wl.W == 0) continue;
+    const int64_t e0 = off[q], n0 = pb.nz_off[q];
+    SpmmArgs a{};
+    a.ptr = pb.ptr + e0 + q;
+    a.idx = pb.idx + n0;
+    a.rid = pb.rid + n0;
+    a.vals = plan->rb.vals + n0;
+    a.X = X;
+    a.ldx = ldx;
+    a.scat = acc;
+    a.lds = lda;
+    a.scat_idx = plan->seg.seg_row + e0;
+    a.scat_mode = 1;
+    a.chunk_row = wl.chunk_row;
+    a.chunk_nz = wl.chunk_nz;
+    a.carry = plan->carry;
+    a.W = wl.W;
+    a.R = (int32_t)(off[q + 1] - e0);
+    a.N = N;
+    if (in_dt == SHIRO_F32) {
+      SHIRO_TRY((run_spmm_family<float, float>(plan, t, &wl, a, vec_for<float>(N, {{X, ldx}, {acc, lda}}), s)));
+    } else {
+      const int v = vec_for<bf16_t>(N, {{X, ldx}}) == 8 && aligned16<float>(acc, lda) ? 8 : 1;
+      SHIRO_TRY((run_spmm_family<bf16_t, float>(plan, t, &wl, a, v, s)));
     }
-    return SHIRO_OK;
-  };
-  using I8 = std::integral_constant<int, 8>;
-  using I4 = std::integral_constant<int, 4>;
-  using I1 = std::integral_constant<int, 1>;
-  using L32 = std::integral_constant<int, 32>;
-  using L64 = std::integral_constant<int, 64>;
-  if (in_dt == SHIRO_F32) {
-    if (vec_for<float>(N, {{X, ldx}, {acc, lda}}) == 4) SHIRO_TRY(run(float{}, L32{}, I4{}));
-    else SHIRO_TRY(run(float{}, L64{}, I1{}));
-  } else {
-    if (vec_for<bf16_t>(N, {{X, ldx}}) == 8 && aligned16<float>(acc, lda)) SHIRO_TRY(run(bf16_t{}, L32{}, I8{}));
-    else SHIRO_TRY(run(bf16_t{}, L64{}, I1{}));
   }
   if (out_dt == SHIRO_BF16) {
     k_round_rows<<<grid_for(plan->rows * (int64_t)N, 65536), kBlock, 0, s>>>(acc, lda, (bf16_t*)Y, ldy,
