@@ -68,12 +68,14 @@ def make_workload(name, dev):
     raise KeyError(name)
 
 
-def src_hash(*names):
-    """Short hash of package files (paths relative to the package)."""
-    h = hashlib.sha256()
-    for n in names:
-        with open(os.path.join(ROOT, "paper_2512_20178_amd", n), "rb") as f:
-            h.update(f.read())
+def src_hash():
+    """Short hash of what fixes the kernels' behaviour: every library source
+    and header (the hash stamped into the library) and the tuning table."""
+    from paper_2512_20178_amd import build
+
+    h = hashlib.sha256(build.source_hash().encode())
+    with open(os.path.join(ROOT, "paper_2512_20178_amd", "tuning_mi355x.txt"), "rb") as f:
+        h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -92,6 +94,7 @@ def main():
     import paper_2512_20178_amd as shiro
     import synth
 
+    shiro._lib.check_build()  # a library built from other sources would time other kernels
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.perf_counter()
@@ -162,6 +165,12 @@ def main():
     gflops = flops_step / (ms_step * 1e-3) / 1e9
     log(f"step {ms_step * 1e3:.1f} us (wall {wall / args.steps * 1e6:.1f} us) -> {gflops:.1f} GFLOP/s")
 
+    # ---- sampled outputs of the timed step (the oracle checks them in the
+    # CPU leg): rows of Y, columns of dB and the value gradients of those rows
+    samples = sample_outputs(A, info, np, torch)
+    step_out = {tdt: take_samples(samples, Y, dB, dvals)}
+    bnz = shiro.block_nnz(plan).cpu().numpy()
+
     # ---- per-kernel durations on the launch stream (HIP events) ----
     sz = 4 if tdt == torch.float32 else 2
     rp = A.row_ptr[info["row_begin"]: info["row_begin"] + M + 1]
@@ -222,7 +231,7 @@ def main():
         with open(pmc_path) as f:
             pmc = json.load(f)
         # counters taken on another build of these kernels or another tuning are stale
-        if pmc.get("src_hash") == src_hash("csrc/spmm.hip", "csrc/common.hpp", "csrc/capi.hip", "tuning_mi355x.txt"):
+        if pmc.get("src_hash") == src_hash():
             traffic = pmc.get("hbm_bytes_per_launch")
     # the product kernel each op ran, from the plan's tuning (group_rows)
     kname = {0: "k_spmm", 1: "k_spmm_grp", 2: "k_spmm_flat", 3: "k_spmm_win"}
@@ -261,6 +270,9 @@ def main():
         "kernels_hbm_frac": {k: round(alg[k] / (kern_us[k] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) for k in kern_us},
         "algorithmic_bytes": {k: int(v) for k, v in alg.items()},
         "setup_ms": {"partition": round(t_part * 1e3, 2), "select_rows": round(t_sel * 1e3, 2)},
+        # per-block sizes: |Cols(A^(p,q))| and nonzeros of each column block
+        "blocks": {"P": A.P, "U_q": spread(np, Uq), "nnz_q": spread(np, bnz),
+                   "nnz_q_lt_1k": int((bnz < 1000).sum()), "nnz_q_gt_200k": int((bnz > 200000).sum())},
     }
 
     # achievable bandwidth of a plain device copy (1 GiB read + 1 GiB written)
@@ -316,6 +328,7 @@ def main():
             if not args.no_autotune:
                 shiro.autotune(plan, N, torch.bfloat16, ops=("spmm", "backward"))
             t_bf = timed(step_bf16)
+            step_out[torch.bfloat16] = take_samples(samples, Yh, dBh, dvals)
             out["bf16_step_us"] = round(t_bf, 2)
             out["bf16_speedup"] = round(ms_step * 1e3 / t_bf, 3)
             out["bf16_kernels_us"] = {
@@ -394,6 +407,8 @@ def main():
         del vp, Bg
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, B, G, N, args, out)
+        # error of each output against the FP64 oracle, beside the BF16 speedup
+        out["precision"] = precision_report(A, B, G, samples, step_out)
 
     print(json.dumps(out), flush=True)
 
@@ -433,6 +448,85 @@ def n_sweep(shiro, synth, plan, A, vals, U, M, tdt, dev, timed, args):
         del Bn, Gn, Bpn, Yn, dBn, dvn
         torch.cuda.empty_cache()
     return res
+
+
+def spread(np, x):
+    x = np.asarray(x, np.int64)
+    return {"min": int(x.min()), "median": int(np.median(x)), "max": int(x.max())} if x.size else {}
+
+
+def sample_outputs(A, info, np, torch):
+    """Host indices of the outputs the precision report checks: 64 rows of
+    the panel (evenly spaced and the longest), 64 columns (those of random
+    nonzeros of the panel and the busiest one) and the panel nonzeros of the
+    sampled rows."""
+    rp = A.row_ptr.cpu().numpy()
+    col = A.col.cpu().numpy()
+    rb, M = info["row_begin"], info["rows"]
+    prp = rp[rb:rb + M + 1]
+    lens = np.diff(prp)
+    rows = np.unique(np.concatenate([np.linspace(0, M - 1, 56).astype(np.int64), np.argsort(lens)[-8:]]))
+    nz0, nz1 = prp[0], prp[-1]
+    rng = np.random.default_rng(11)
+    pcol = col[nz0:nz1]
+    busiest = np.argmax(np.bincount(pcol, minlength=A.n_cols)) if pcol.size else 0
+    cols = np.unique(np.concatenate([pcol[rng.integers(0, max(pcol.size, 1), 63)] if pcol.size else [], [busiest]]))
+    ks = np.concatenate([np.arange(prp[r], prp[r + 1]) for r in rows]) if rows.size else np.zeros(0, np.int64)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).long().to(A.col.device)
+    return {"rows": rows, "cols": cols.astype(np.int64), "ks": ks.astype(np.int64), "rp": rp, "col": col,
+            "rows_t": t(rows), "cols_t": t(cols), "ks_t": t(ks)}
+
+
+def take_samples(smp, Y, dB, dvals):
+    return (Y.index_select(0, smp["rows_t"]).float().cpu().numpy(),
+            dB.index_select(0, smp["cols_t"]).float().cpu().numpy(),
+            dvals.index_select(0, smp["ks_t"]).cpu().numpy())
+
+
+def precision_report(A, B, G, smp, step_out):
+    """Max relative error (componentwise, |A||B|-normalised) of the sampled
+    outputs of each timed step against the FP64 oracle on the original
+    float32 inputs: Y rows, dB columns (A^T dY) and the dvals of the
+    sampled rows."""
+    import numpy as np
+    import torch
+
+    import oracle
+
+    rp, col, rows, cols, ks = smp["rp"], smp["col"], smp["rows"], smp["cols"], smp["ks"]
+    vals = A.vals.cpu().numpy()
+    M = G.shape[0]
+    rb = A.p * (-(-A.n_rows // A.P))
+    # the sampled rows as a CSR of their own over the columns they touch
+    scols = np.unique(col[ks]) if ks.size else np.zeros(0, np.int64)
+    remap = np.zeros(A.n_cols, np.int32)
+    remap[scols] = np.arange(scols.size, dtype=np.int32)
+    srp = np.concatenate([[0], np.cumsum([rp[rb + r + 1] - rp[rb + r] for r in rows])]).astype(np.int64)
+    sub = oracle.Csr(len(rows), max(scols.size, 1), srp, remap[col[ks]], vals[ks], 1, 0)
+    Bs = B.index_select(0, torch.from_numpy(scols).long().to(B.device)).float().cpu().numpy()
+    Gs = G.index_select(0, torch.from_numpy(rows).long().to(G.device)).float().cpu().numpy()
+    srows = np.arange(len(rows))
+    y_ref, y_den = oracle.spmm_rows(sub, srows, Bs, None), oracle.spmm_rows(sub, srows, Bs, None, abs_mode=True)
+    dv_ref, dv_den = oracle.sddmm(sub, Gs, Bs, None), oracle.sddmm(sub, Gs, Bs, None, abs_mode=True)
+    # columns of A^T dY: the panel's nonzeros in the sampled columns
+    nz0, nz1 = rp[rb], rp[rb + M]
+    slot = np.full(A.n_cols, -1, np.int32)
+    slot[cols] = np.arange(cols.size, dtype=np.int32)
+    keep = slot[col[nz0:nz1]] >= 0
+    kept_before = np.concatenate([[0], np.cumsum(keep, dtype=np.int64)])
+    trp = kept_before[rp[rb:rb + M + 1] - nz0]
+    tsub = oracle.Csr(M, cols.size, trp, slot[col[nz0:nz1]][keep], vals[nz0:nz1][keep], 1, 0)
+    Gh = G.float().cpu().numpy()
+    db_ref, db_den = oracle.spmm_t(tsub, Gh, None), oracle.spmm_t(tsub, Gh, None, abs_mode=True)
+    rep = {"metric": "max |out - oracle| / (|A||B|, |A|^T|dY|, sum |dY||B|), sampled outputs, FP64 oracle "
+                     "on the float32 inputs",
+           "samples": {"Y_rows": int(len(rows)), "dB_cols": int(cols.size), "dvals": int(ks.size)}}
+    for dt, (y, db, dv) in step_out.items():
+        rep["bf16" if dt == torch.bfloat16 else "f32"] = {
+            "Y": oracle.rel_err(y, y_ref, y_den), "dB": oracle.rel_err(db, db_ref, db_den),
+            "dvals": oracle.rel_err(dv, dv_ref, dv_den)}
+    rep["bounds"] = {"f32": 1e-5, "bf16": 1e-2}
+    return rep
 
 
 def cpu_baseline(A, B, G, N, args, out):

@@ -155,6 +155,11 @@ typedef struct {
 /* Library version, 10000*major + 100*minor + patch. */
 SHIRO_API int shiro_version(void);
 
+/* Hash of the sources this library was built from (16 hex digits of the
+ * sha256 of every HIP source and header and of this header), so that a
+ * caller can tell a library built from other sources.  Static string. */
+SHIRO_API const char* shiro_build_hash(void);
+
 /* Text of the calling thread's last error ("" if none).  Valid until the
  * thread's next failing call. */
 SHIRO_API const char* shiro_last_error(void);

@@ -79,6 +79,7 @@ EXPORTS = [
     "shiro_set_allocator",
     "shiro_plan_destroy",
     "shiro_spmm_noalloc",
+    "shiro_build_hash",
 ]
 
 # shiro_alloc_fn / shiro_free_fn
@@ -143,6 +144,7 @@ def load(path: str = LIB_PATH):
         L = ctypes.CDLL(path)
         L.shiro_version.restype = ctypes.c_int
         L.shiro_last_error.restype = ctypes.c_char_p
+        L.shiro_build_hash.restype = ctypes.c_char_p
         L.shiro_partition.argtypes = [_i64, _i64, _i64, _p, _p, _i32, _i32, _u32, _p, ctypes.POINTER(_p)]
         L.shiro_plan_info.argtypes = [_p, ctypes.POINTER(PlanInfo)]
         L.shiro_block_nnz.argtypes = [_p, _p, _p]
@@ -173,10 +175,27 @@ def load(path: str = LIB_PATH):
         L.shiro_plan_destroy.argtypes = [_p]
         L.shiro_spmm_noalloc.argtypes = [_p, _p, _p, _i64, _i32, ctypes.c_int, _p, _i64, ctypes.c_int, _p]
         for name in EXPORTS:
-            if name != "shiro_last_error":
+            if name not in ("shiro_last_error", "shiro_build_hash"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
         return _lib
+
+
+def build_hash() -> str:
+    """Source hash stamped into the loaded library."""
+    return load().shiro_build_hash().decode()
+
+
+def check_build(strict: bool = True) -> bool:
+    """True when the loaded library was built from the sources in the tree;
+    with strict, a mismatch raises (the library is stale: rebuild it)."""
+    from . import build as _build
+
+    ok = build_hash() == _build.source_hash()
+    if not ok and strict:
+        raise ImportError(f"{LIB_PATH} was built from other sources (stamp {build_hash()}, tree "
+                          f"{_build.source_hash()}): rebuild with `python -m paper_2512_20178_amd.build`")
+    return ok
 
 
 def check(rc: int) -> None:

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import glob
+import hashlib
 import os
 import shutil
 import subprocess
@@ -21,6 +22,7 @@ OBJ = os.path.join(PKG, "_build")
 ARCH = os.environ.get("SHIRO_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
 FLAGS = [
     f"--offload-arch={ARCH}",
     "-O3",
@@ -30,6 +32,32 @@ FLAGS = [
     # keep the compiler from forming packed-FP32 (v_pk_*_f32) instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
+
+
+def source_hash() -> str:
+    """sha256 (16 hex digits) of every source the library is built from: the
+    HIP files, their headers and the C ABI header, in a fixed order."""
+    files = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.hpp")))
+    files.append(os.path.join(PKG, "..", "include", "shiro.h"))
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _buildinfo(digest: str) -> str:
+    """A one-function object that stamps the source hash into the library."""
+    src = os.path.join(OBJ, "buildinfo.cpp")
+    with open(src, "w") as f:
+        f.write('extern "C" __attribute__((visibility("default"))) const char* shiro_build_hash(void) {\n'
+                f'  return "{digest}";\n}}\n')
+    obj = src + ".o"
+    r = subprocess.run([HIPCC, "-O2", "-fPIC", "-c", src, "-o", obj], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compiling the build stamp failed:\n{r.stderr}")
+    return obj
 
 
 def _compile(src: str) -> str:
@@ -60,8 +88,10 @@ def build(verbose: bool = True, incremental: bool = False) -> str:
     with cf.ThreadPoolExecutor(jobs) as ex:
         list(ex.map(_compile, todo))
     objs = [os.path.join(OBJ, os.path.basename(f) + ".o") for f in srcs]
+    objs.append(_buildinfo(source_hash()))
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+           f"-L{ROCM_LIB}", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM_LIB}"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

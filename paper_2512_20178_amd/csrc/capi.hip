@@ -11,11 +11,22 @@
 #include <unordered_map>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "plan.hpp"
 
 namespace shiro {
 
 static thread_local std::string g_last_error;
+
+// A roctx range around one call of the path (host side: it brackets the
+// enqueue of the call's kernels; visible with rocprofv3 --marker-trace).
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 int set_error(int code, const std::string& msg) {
   g_last_error = msg;
@@ -677,6 +688,7 @@ SHIRO_API int shiro_block_nnz(shiro_plan plan, int64_t* d_block_nnz, shiro_strea
 
 SHIRO_API int shiro_select_rows(shiro_plan plan, shiro_stream_t stream, int64_t* h_U_total,
                                 int64_t* h_U_per_block) {
+  TraceRange range_("shiro.select_rows");
   if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "select_rows: plan is NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (!plan->selected) {
@@ -690,6 +702,7 @@ SHIRO_API int shiro_select_rows(shiro_plan plan, shiro_stream_t stream, int64_t*
 }
 
 SHIRO_API int shiro_refresh_selection(shiro_plan plan, shiro_stream_t stream) {
+  TraceRange range_("shiro.select_rows(refresh)");
   if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "refresh_selection: plan is NULL");
   if (!plan->selected) return set_error(SHIRO_ERR_NOT_READY, "refresh_selection: call shiro_select_rows first");
   return run_select(plan, reinterpret_cast<hipStream_t>(stream), false);
@@ -721,6 +734,7 @@ SHIRO_API int shiro_copy_selection(shiro_plan plan, int32_t* d_unique_cols, int6
 
 SHIRO_API int shiro_pack_B(shiro_plan plan, const void* d_B, int64_t ldb, int32_t N, shiro_dtype dt,
                            void* d_Bpacked, int64_t ldp, shiro_stream_t stream) {
+  TraceRange range_("shiro.pack_B");
   if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "pack_B: plan is NULL");
   if (!plan->selected) return set_error(SHIRO_ERR_NOT_READY, "pack_B: call shiro_select_rows first");
   if (!valid_dt(dt)) return set_error(SHIRO_ERR_UNSUPPORTED, "pack_B: unknown dtype");
@@ -732,6 +746,7 @@ SHIRO_API int shiro_pack_B(shiro_plan plan, const void* d_B, int64_t ldb, int32_
 SHIRO_API int shiro_spmm(shiro_plan plan, const float* d_vals, const void* d_Bpacked, int64_t ldp,
                          int32_t N, shiro_dtype in_dt, void* d_Y, int64_t ldy, shiro_dtype out_dt,
                          uint32_t mode, shiro_stream_t stream) {
+  TraceRange range_("shiro.spmm");
   if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "spmm: plan is NULL");
   if (!plan->selected) return set_error(SHIRO_ERR_NOT_READY, "spmm: call shiro_select_rows first");
   if (!valid_dt(in_dt) || !valid_dt(out_dt)) return set_error(SHIRO_ERR_UNSUPPORTED, "spmm: unknown dtype");
@@ -752,6 +767,7 @@ SHIRO_API int shiro_spmm_backward(shiro_plan plan, const float* d_vals, const vo
                                   const void* d_Bpacked, int64_t ldp, int32_t N, shiro_dtype dt,
                                   void* d_dBpacked, int64_t lddbp, void* d_dB, int64_t lddb,
                                   float* d_dvals, uint32_t flags, shiro_stream_t stream) {
+  TraceRange range_("shiro.spmm_backward");
   if (!plan) return set_error(SHIRO_ERR_INVALID_ARG, "spmm_backward: plan is NULL");
   if (flags & ~SHIRO_DB_OVERWRITE) return set_error(SHIRO_ERR_INVALID_ARG, "spmm_backward: unknown flags");
   if (!plan->selected) return set_error(SHIRO_ERR_NOT_READY, "spmm_backward: call shiro_select_rows first");

@@ -52,6 +52,15 @@ def test_library_is_built_for_gfx950():
     assert b"gfx950" in data
 
 
+def test_library_stamp_matches_the_sources(lib):
+    """The library in the tree was built from the sources in the tree."""
+    from paper_2512_20178_amd import _lib, build
+
+    assert len(build.source_hash()) == 16
+    assert _lib.build_hash() == build.source_hash()
+    assert _lib.check_build(strict=False)
+
+
 def test_version(lib):
     assert lib.shiro_version() == 10000
 
