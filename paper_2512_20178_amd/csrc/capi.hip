@@ -13,6 +13,7 @@
 
 #include <rocprofiler-sdk-roctx/roctx.h>
 
+#include "mvc.hpp"
 #include "plan.hpp"
 
 namespace shiro {
@@ -862,18 +863,9 @@ SHIRO_API int shiro_aggregate_c(shiro_plan plan, const void* d_Cp, int64_t ldc, 
 SHIRO_API int shiro_mvc_bipartite(int64_t n_left, int64_t n_right, int64_t n_edges, const int32_t* h_left,
                                   const int32_t* h_right, const int64_t* h_w_left, const int64_t* h_w_right,
                                   uint8_t* h_cover_left, uint8_t* h_cover_right, int64_t* h_weight) {
-  if (n_left < 0 || n_right < 0 || n_edges < 0 || n_left + n_right > (1 << 30))
-    return set_error(SHIRO_ERR_INVALID_ARG, "mvc_bipartite: bad sizes");
-  if (!h_weight || (n_left > 0 && !h_cover_left) || (n_right > 0 && !h_cover_right) ||
-      (n_edges > 0 && (!h_left || !h_right)))
-    return set_error(SHIRO_ERR_INVALID_ARG, "mvc_bipartite: NULL pointer");
-  for (int64_t e = 0; e < n_edges; ++e)
-    if (h_left[e] < 0 || h_left[e] >= n_left || h_right[e] < 0 || h_right[e] >= n_right)
-      return set_error(SHIRO_ERR_INVALID_ARG, "mvc_bipartite: edge endpoint out of range");
-  for (int64_t i = 0; h_w_left && i < n_left; ++i)
-    if (h_w_left[i] < 0) return set_error(SHIRO_ERR_INVALID_ARG, "mvc_bipartite: negative weight");
-  for (int64_t j = 0; h_w_right && j < n_right; ++j)
-    if (h_w_right[j] < 0) return set_error(SHIRO_ERR_INVALID_ARG, "mvc_bipartite: negative weight");
+  if (const char* why = mvc::arg_error(n_left, n_right, n_edges, h_left, h_right, h_w_left, h_w_right,
+                                       h_cover_left, h_cover_right, h_weight))
+    return set_error(SHIRO_ERR_INVALID_ARG, std::string("mvc_bipartite: ") + why);
   return solve_mvc(n_left, n_right, n_edges, h_left, h_right, h_w_left, h_w_right, h_cover_left,
                    h_cover_right, h_weight);
 }
