@@ -164,20 +164,27 @@ struct PopcountIn {
   __device__ int64_t operator()(int64_t w) const { return __popc(bits[w]); }
 };
 
-// Down pass of the selection scan: a workgroup owns 512 words (two per
-// thread); it scans their popcounts (plus the tile offset from the tile
-// scan), writes the word table entries (bits, packed position of the word's
-// first set bit) that the remap reads, clears the bitmap words it read, and
-// compacts the ids of the set bits: each lane writes its words' ids into the
-// tile's slice of an LDS buffer, then the workgroup copies the slice to
-// unique_cols with consecutive lanes on consecutive ids.
-constexpr int kSelItems = 2;
+// Down pass of the selection scan: a workgroup owns 256 words (one per
+// thread).  Its offset is the sum of the earlier tiles' popcount totals
+// (summed here, so no separate pass scans the tile totals; the last tile
+// also writes U).  It scans its words' popcounts, writes the word table
+// entries (bits, packed position of the word's first set bit) that the
+// remap reads, clears the bitmap words it read, and compacts the ids of the
+// set bits: each lane writes its word's ids into the tile's slice of an LDS
+// buffer, then the workgroup copies the slice to unique_cols with
+// consecutive lanes on consecutive ids.
+constexpr int kSelItems = 1;
 
 __global__ __launch_bounds__(kBlock) void k_select_down(uint32_t* __restrict__ bits, uint32_t* __restrict__ wtab,
-                                                        int64_t n_words, const int64_t* __restrict__ tile_off,
-                                                        int32_t* __restrict__ unique_cols) {
+                                                        int64_t n_words, const int64_t* __restrict__ tile_sums,
+                                                        int64_t* __restrict__ d_U, int32_t* __restrict__ unique_cols) {
   __shared__ int64_t lds[kWavesPerBlock];
   __shared__ int32_t ids[kBlock * kSelItems * 32];  // at most 32 ids per word
+  // this tile's offset: the sum of the earlier tiles' totals
+  int64_t before = 0;
+  for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kBlock) before += tile_sums[i];
+  int64_t toff;
+  (void)block_exclusive_scan<int64_t>(before, lds, &toff);
   const int64_t w0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kSelItems;
   uint32_t v[kSelItems];
   int64_t cnt = 0;
@@ -188,7 +195,7 @@ __global__ __launch_bounds__(kBlock) void k_select_down(uint32_t* __restrict__ b
   }
   int64_t tot;
   int32_t o = (int32_t)block_exclusive_scan<int64_t>(cnt, lds, &tot);
-  const int64_t toff = tile_off[blockIdx.x];
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *d_U = toff + tot;
 #pragma unroll
   for (int i = 0; i < kSelItems; ++i) {
     const int64_t w = w0 + i;
@@ -380,8 +387,10 @@ static int build_bins(shiro_plan plan, hipStream_t s) {
   std::vector<int64_t> h((size_t)nbins + 1);
   SHIRO_HIP(hipMemcpyAsync(h.data(), off, (size_t)(nbins + 1) * 8, hipMemcpyDeviceToHost, s));
   SHIRO_HIP(hipStreamSynchronize(s));
-  // about two chunks per compute unit, 2048 to 65536 ids each
-  const int64_t chunk = std::min<int64_t>(std::max<int64_t>(ceil_div(nnz, 2 * (int64_t)plan->num_cus), 2048), 65536);
+  // about one chunk per compute unit, 2048 to 65536 ids each (each chunk
+  // ends with a pass over its bin's 4096 bitmap words, so fewer, larger
+  // chunks mark faster: 2^24 R-MAT panel 20 us at four per CU, 15 at two)
+  const int64_t chunk = std::min<int64_t>(std::max<int64_t>(ceil_div(nnz, (int64_t)plan->num_cus), 2048), 65536);
   std::vector<int32_t> items;
   for (int64_t b = 0; b < nbins; ++b)
     for (int64_t st = h[b]; st < h[b + 1]; st += chunk) {
@@ -415,14 +424,13 @@ int run_select(shiro_plan plan, hipStream_t s, bool sync) {
     k_mark_bins<<<plan->n_mark_items, kBlock, 0, s>>>(plan->bcol, plan->mark_items, plan->bits, nw);
     SHIRO_LAUNCH_CHECK();
   }
-  // reduce-then-scan over the word popcounts; the down pass compacts the ids
+  // per-tile popcount totals, then the down pass (tile offsets, word table,
+  // compaction of the ids)
   const int64_t ntiles = scan_tiles_of(nw, kSelItems);
   int64_t* sums = reinterpret_cast<int64_t*>(scan_tmp);
   k_scan_reduce<kSelItems, PopcountIn><<<dim3((unsigned)ntiles), kBlock, 0, s>>>(PopcountIn{plan->bits}, nw, sums);
   SHIRO_LAUNCH_CHECK();
-  k_scan_tiles<<<1, kBlock, 0, s>>>(sums, ntiles, d_U);
-  SHIRO_LAUNCH_CHECK();
-  k_select_down<<<dim3((unsigned)ntiles), kBlock, 0, s>>>(plan->bits, plan->wtab, nw, sums, plan->unique_cols);
+  k_select_down<<<dim3((unsigned)ntiles), kBlock, 0, s>>>(plan->bits, plan->wtab, nw, sums, d_U, plan->unique_cols);
   SHIRO_LAUNCH_CHECK();
   k_remap<<<grid_for(std::max<int64_t>((nnz + 3) / 4, (int64_t)plan->P + 1)), kBlock, 0, s>>>(
       plan->col, nnz, plan->wtab, plan->colmap, plan->n_cols, plan->K, plan->P, d_U, plan->block_off);

@@ -6,6 +6,8 @@ indices, offsets and packed bytes bit-exactly; float32 outputs within 1e-5
 and bfloat16 outputs within 1e-2 of the oracle, relative to the oracle's
 absolute product (|A||B|, |A|^T|dY|, sum |dY||B|) entry by entry.
 """
+import gc
+
 import numpy as np
 import pytest
 import torch
@@ -759,6 +761,9 @@ def test_torch_allocator(shiro):
     B = synth.dense(A.n_cols, N, 0, synth.STREAM_B).to(dev)
     G = None
     Ac = oracle.Csr.from_synth(A)
+    # tensors of earlier tests that are only cyclic garbage would otherwise be
+    # freed in the middle of this test and move the baseline
+    gc.collect()
     torch.cuda.synchronize()
     base = torch.cuda.memory_allocated()
     shiro.use_torch_allocator(True)
