@@ -144,6 +144,11 @@ typedef struct {
                        * not for the sampled product, SHIRO_KERNEL_SDDMM)      */
   int32_t xcd_remap; /* 1: give each XCD a contiguous range of work            */
   int32_t wg_per_cu; /* persistent grid: workgroups per compute unit           */
+  int32_t lds_rows;  /* windowed walk (group_rows 3) of SHIRO_KERNEL_SPMM and
+                      * SHIRO_KERNEL_SPMM_T only: the lds_rows most referenced
+                      * rows of the gathered operand (Bpacked, resp. dY) are
+                      * copied into each workgroup's LDS and read from there;
+                      * 0 = off, at most 128 and 64 KB per workgroup          */
 } shiro_tuning_t;
 
 #define SHIRO_KERNEL_SPMM 0

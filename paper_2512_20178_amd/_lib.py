@@ -118,6 +118,7 @@ class Tuning(ctypes.Structure):
         ("group_rows", ctypes.c_int32),
         ("xcd_remap", ctypes.c_int32),
         ("wg_per_cu", ctypes.c_int32),
+        ("lds_rows", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -228,6 +228,7 @@ shiro_tuning_t default_tuning(int kernel, int32_t, shiro_dtype) {
   t.group_rows = walk ? 2 : 0;
   t.xcd_remap = 0;
   t.wg_per_cu = walk ? 16 : 8;
+  t.lds_rows = 0;
   return t;
 }
 
@@ -244,6 +245,9 @@ int validate_tuning(int kernel, int32_t, shiro_dtype, const shiro_tuning_t& t) {
     return set_error(SHIRO_ERR_INVALID_ARG, "tuning: the sampled product has no nonzero walk (group_rows 0 or 1)");
   if (t.xcd_remap != 0 && t.xcd_remap != 1) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: xcd_remap must be 0 or 1");
   if (t.wg_per_cu < 1 || t.wg_per_cu > 32) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: wg_per_cu outside [1, 32]");
+  if (t.lds_rows < 0 || t.lds_rows > 128) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: lds_rows outside [0, 128]");
+  if (t.lds_rows > 0 && (t.group_rows != 3 || (kernel != SHIRO_KERNEL_SPMM && kernel != SHIRO_KERNEL_SPMM_T)))
+    return set_error(SHIRO_ERR_INVALID_ARG, "tuning: lds_rows needs the windowed walk (group_rows 3) of spmm or spmm_t");
   return SHIRO_OK;
 }
 
@@ -305,6 +309,10 @@ static void plan_free(shiro_plan plan) {
   dev_free(plan->rb.iota);
   dev_free(plan->rb.vals);
   dev_free(plan->rb.block_off);
+  for (auto& kv : plan->hot) {
+    dev_free(kv.second.walk_idx);
+    dev_free(kv.second.hot_src);
+  }
   dev_free(plan->pb.ptr);
   dev_free(plan->pb.idx);
   dev_free(plan->pb.rid);
@@ -368,6 +376,7 @@ static bool cache_lookup(const std::string& key, shiro_tuning_t* t) {
     std::string k;
     shiro_tuning_t c;
     if (is >> k >> c.chunk >> c.lanes >> c.unroll >> c.group_rows >> c.xcd_remap >> c.wg_per_cu) {
+      if (!(is >> c.lds_rows)) c.lds_rows = 0;  // lines written before the knob existed
       if (k == key) {
         *t = c;
         found = true;  // last entry wins
@@ -382,7 +391,7 @@ static void cache_store(const std::string& key, const shiro_tuning_t& t) {
   if (!path || !*path) return;
   std::ofstream f(path, std::ios::app);
   f << key << ' ' << t.chunk << ' ' << t.lanes << ' ' << t.unroll << ' ' << t.group_rows << ' '
-    << t.xcd_remap << ' ' << t.wg_per_cu << '\n';
+    << t.xcd_remap << ' ' << t.wg_per_cu << ' ' << t.lds_rows << '\n';
 }
 
 // Median of 9 timed runs after one warm-up (the warm-up also builds any
@@ -514,6 +523,16 @@ static int tune_one(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt, Tune
       t.chunk = fit_chunk(plan, kernel, N, dt, t, m);
       if (t.chunk > 0) SHIRO_TRY(consider(t));
     }
+  // stage 5: the most referenced rows of the gathered operand in LDS
+  // (windowed walk of spmm and spmm_t); rows of at most 1 KB, so 64 fit
+  if (best.group_rows == 3 && (kernel == SHIRO_KERNEL_SPMM || kernel == SHIRO_KERNEL_SPMM_T)) {
+    const shiro_tuning_t base5 = best;
+    for (int H : {16, 32, 64}) {
+      shiro_tuning_t t = base5;
+      t.lds_rows = H;
+      SHIRO_TRY(consider(t));
+    }
+  }
   plan->tuning[TuneKey{kernel, N, (int)dt}] = best;
   cache_store(key, best);
   return SHIRO_OK;
@@ -896,6 +915,8 @@ SHIRO_API int shiro_prepare(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t
     SHIRO_TRY(ensure_rows_work(plan, t.chunk, true, s, &wl));
     SHIRO_TRY(ensure_carry(plan, (int64_t)wl->W * 2 * N, true));
     SHIRO_TRY(ensure_row_rid(plan, true, s));
+    const HotRows* hot;
+    if (t.group_rows == 3 && t.lds_rows > 0) SHIRO_TRY(ensure_hot(plan, SHIRO_KERNEL_SPMM, t.lds_rows, true, s, &hot));
   }
   if (ops & SHIRO_OP_BACKWARD) {
     SHIRO_TRY(build_transposed(plan, s));
@@ -903,6 +924,8 @@ SHIRO_API int shiro_prepare(shiro_plan plan, int32_t N, shiro_dtype dt, uint32_t
     const shiro_tuning_t t = tuning_for(plan, SHIRO_KERNEL_SPMM_T, N, dt);
     SHIRO_TRY(ensure_cols_work(plan, t.chunk, true, s, &wl));
     SHIRO_TRY(ensure_carry(plan, (int64_t)wl->W * 2 * N, true));
+    const HotRows* hot;
+    if (t.group_rows == 3 && t.lds_rows > 0) SHIRO_TRY(ensure_hot(plan, SHIRO_KERNEL_SPMM_T, t.lds_rows, true, s, &hot));
     const shiro_tuning_t t2 = tuning_for(plan, SHIRO_KERNEL_SDDMM, N, dt);
     SHIRO_TRY(ensure_rows_work(plan, t2.chunk, true, s, &wl));
   }

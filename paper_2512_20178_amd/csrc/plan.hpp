@@ -82,6 +82,15 @@ struct PerBlock {
   int32_t max_W = 0;
 };
 
+// Hot rows of a gathered operand kept in LDS by the windowed walk: the H most
+// referenced rows (hot_src, by reference count, ties by index), and the
+// walk's index array with every reference to them replaced by -(slot + 1).
+struct HotRows {
+  int32_t* walk_idx = nullptr;  // nnz
+  int32_t* hot_src = nullptr;   // H
+  int32_t H = 0;
+};
+
 struct TuneKey {
   int kernel, N, dt;
   bool operator<(const TuneKey& o) const {
@@ -134,6 +143,8 @@ struct shiro_plan_s {
   shiro::PerBlock pb;
   std::map<int32_t, shiro::WorkList> rb_work;   // keyed by chunk size (partial C rows)
   std::map<int32_t, shiro::WorkList> agg_work;  // keyed by chunk size (sum into the panel)
+  // hot-row index arrays keyed by (kernel family, H)
+  std::map<std::pair<int32_t, int32_t>, shiro::HotRows> hot;
 
   // carry slots of split rows: 2 * W * carry_cols floats
   float* carry = nullptr;
@@ -273,6 +284,10 @@ int ensure_cols_work(shiro_plan plan, int32_t chunk, bool allocate, hipStream_t 
 int ensure_carry(shiro_plan plan, int64_t elems, bool allocate);
 int ensure_acc32(shiro_plan plan, int64_t elems, bool allocate);
 int ensure_tvals(shiro_plan plan, bool allocate);
+// The hot-row arrays of kernel SHIRO_KERNEL_SPMM or _SPMM_T for H slots
+// (setup: copies the index array to the host; NOT_READY/CAPTURING when
+// allocate is false and they are missing).
+int ensure_hot(shiro_plan plan, int kernel, int32_t H, bool allocate, hipStream_t s, const HotRows** out);
 
 shiro_tuning_t default_tuning(int kernel, int32_t N, shiro_dtype dt);
 // The tuning a plan uses for one kernel family (its own, else the default).

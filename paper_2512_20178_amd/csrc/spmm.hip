@@ -15,6 +15,9 @@
 // groups of a wavefront take consecutive nonzeros of the same row, UNROLL
 // deep, and are reduced with cross-lane shuffles when the row ends.  All row
 // bookkeeping is wavefront-uniform and lives in scalar registers.
+#include <algorithm>
+#include <vector>
+
 #include "plan.hpp"
 #include "scan.hpp"
 
@@ -119,6 +122,8 @@ struct SpmmArgs {
   const int32_t* chunk_row;  // W + 1
   const int32_t* chunk_nz;   // W + 1
   const int32_t* rid;       // nnz: row of each nonzero (only for patterns without empty rows)
+  const int32_t* hot_src;   // windowed walk: rows of X kept in LDS (idx = -(slot + 1) reads slot)
+  int32_t n_hot;
   float* carry;             // [W][2][N]
   int32_t W, R, N;
   int32_t chunks_per_wave;
@@ -133,14 +138,15 @@ struct SpmmArgs {
       TOUT *__restrict__ scat, int64_t lds, const int32_t *__restrict__ scat_idx,             \
       const int32_t *__restrict__ chunk_row, const int32_t *__restrict__ chunk_nz,            \
       const int32_t *__restrict__ rid, float *__restrict__ carry, int32_t W, int32_t R,         \
-      int32_t N, int32_t cpw, int32_t xcd_remap, int32_t scat_mode
+      int32_t N, int32_t cpw, int32_t xcd_remap, int32_t scat_mode,                             \
+      const int32_t *__restrict__ hot_src, int32_t n_hot
 
 #define SHIRO_SPMM_ARGS(TIN, TOUT, a)                                                          \
   (a).ptr, (a).idx, (a).vals, reinterpret_cast<const TIN*>((a).D), (a).ldd, (a).dot_out,      \
       reinterpret_cast<const TIN*>((a).X), (a).ldx,                                            \
       reinterpret_cast<TOUT*>((a).out), (a).ldo, reinterpret_cast<TOUT*>((a).scat), (a).lds,   \
       (a).scat_idx, (a).chunk_row, (a).chunk_nz, (a).rid, (a).carry, (a).W, (a).R, (a).N,     \
-      (a).chunks_per_wave, (a).xcd_remap, (a).scat_mode
+      (a).chunks_per_wave, (a).xcd_remap, (a).scat_mode, (a).hot_src, (a).n_hot
 
 template <typename TOUT, int VEC>
 __device__ __forceinline__ void epilogue_row(TOUT* __restrict__ out, int64_t ldo, TOUT* __restrict__ scat,
@@ -622,6 +628,11 @@ __global__ __launch_bounds__(kBlock) void k_spmm_flat(SHIRO_SPMM_PARAMS(TIN, TOU
 // window ahead.  With DOT, the dense row D[r] is loaded only when the row
 // changes (runs of a packed column's nonzeros share it), and the dots are
 // collected in the window's lanes and written with one store per window.
+// With n_hot > 0 the workgroup first copies rows hot_src[0..n_hot) of X (its
+// column tile) into LDS, and an index -(slot + 1) in idx reads that slot
+// instead of X: the most referenced rows are then served from LDS (the
+// tuning knob lds_rows; the index arrays with marked slots are built at
+// setup).
 template <typename T>
 __device__ __forceinline__ T lane_pull(int src_lane, T v) {
   static_assert(sizeof(T) == 4, "32-bit values");
@@ -642,6 +653,23 @@ __global__ __launch_bounds__(kBlock) void k_spmm_win(SHIRO_SPMM_PARAMS(TIN, TOUT
   const bool cvalid = c < N;
   const int64_t cl = cvalid ? c : 0;
 
+  // hot rows: slot h holds the tile's LANES*VEC elements of X row hot_src[h]
+  extern __shared__ __align__(16) unsigned char hot_lds[];
+  TIN* const hot = reinterpret_cast<TIN*>(hot_lds);
+  constexpr int TW = LANES * VEC;
+  if (n_hot > 0) {
+    const int64_t c0 = (int64_t)blockIdx.y * TW;
+    for (int i = threadIdx.x; i < n_hot * LANES; i += kBlock) {
+      const int h = i / LANES, l = i % LANES;
+      const int64_t cc = c0 + (int64_t)l * VEC;
+      TIN* dst = hot + (int64_t)h * TW + l * VEC;
+      if (cc < N) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) dst[e] = X[(int64_t)hot_src[h] * ldx + cc + e];
+      }
+    }
+    __syncthreads();
+  }
   const int64_t worker = (int64_t)uniform(logical_block(xcd_remap) * kWavesPerBlock + wave_id()) * G + g;
   const int64_t wb = worker * cpw;
   const int64_t we = wb + cpw < W ? wb + cpw : W;
@@ -729,7 +757,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_win(SHIRO_SPMM_PARAMS(TIN, TOUT
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
           ok[u] = k + u < j1;
-          Elem<TIN>::template load<VEC>(X + (int64_t)xi[u] * ldx + cl, x[u]);
+          if (xi[u] < 0) Elem<TIN>::template load<VEC>(hot + (int64_t)(-xi[u] - 1) * TW + li * VEC, x[u]);
+          else Elem<TIN>::template load<VEC>(X + (int64_t)xi[u] * ldx + cl, x[u]);
         }
         float d[DOT ? UNROLL : 1][VEC];
         if constexpr (DOT) {
@@ -1290,7 +1319,8 @@ int spmm_dispatch(const shiro_tuning_t& t, dim3 grid, hipStream_t s, const SpmmA
 #define SHIRO_SPMM_CASE(L, U)                                                                          \
   if (t.lanes == L && t.unroll == U) {                                                                 \
     if (t.group_rows == 3 && a.rid)                                                                    \
-      k_spmm_win<TIN, TOUT, L, VEC, U, DOT, SCAT><<<grid, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a)); \
+      k_spmm_win<TIN, TOUT, L, VEC, U, DOT, SCAT><<<grid, kBlock, (size_t)a.n_hot * L * VEC * sizeof(TIN), s>>>( \
+          SHIRO_SPMM_ARGS(TIN, TOUT, a));                                                             \
     else if (t.group_rows == 2 && a.rid)                                                               \
       k_spmm_flat<TIN, TOUT, L, VEC, U, DOT, SCAT><<<grid, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a)); \
     else if (t.group_rows)                                                                             \
@@ -1345,6 +1375,8 @@ int run_spmm_family(shiro_plan plan, shiro_tuning_t t, const WorkList* wl, SpmmA
   SHIRO_TRY(grid_waves(plan, t, wl->W, workers, &a.chunks_per_wave, &nb));
   const int ntiles = (int)ceil_div(a.N, (int64_t)t.lanes * vec);
   a.xcd_remap = t.xcd_remap;
+  if (a.n_hot > 0 && (int64_t)a.n_hot * t.lanes * vec * (int64_t)sizeof(TIN) > 65536)
+    return set_error(SHIRO_ERR_UNSUPPORTED, "spmm: lds_rows rows of this width exceed 64 KB of LDS");
   dim3 grid(nb, ntiles);
   constexpr int V16 = Elem<TIN>::kVec16;
   const bool store = a.scat_mode == 2;
@@ -1616,8 +1648,13 @@ int launch_pattern(shiro_plan plan, const shiro_tuning_t& t, const WorkList* wl,
                    const int32_t* idx, const float* vals, int64_t R, const void* X, int64_t ldx,
                    int32_t N, shiro_dtype in_dt, void* Y, int64_t ldy, shiro_dtype out_dt,
                    hipStream_t s, const int32_t* add_rows = nullptr, const int32_t* rid = nullptr,
-                   float* carry = nullptr) {
+                   float* carry = nullptr, const HotRows* hot = nullptr) {
   SpmmArgs a{};
+  if (hot) {  // the windowed walk reads the hot rows from LDS
+    idx = hot->walk_idx;
+    a.hot_src = hot->hot_src;
+    a.n_hot = hot->H;
+  }
   a.ptr = ptr;
   a.rid = rid;
   a.idx = idx;
@@ -1664,6 +1701,47 @@ static const float* plan_values(shiro_plan plan, const float* vals, hipStream_t 
   return plan->svals;
 }
 
+int ensure_hot(shiro_plan plan, int kernel, int32_t H, bool allocate, hipStream_t s, const HotRows** out) {
+  const auto key = std::make_pair((int32_t)kernel, H);
+  auto it = plan->hot.find(key);
+  if (it != plan->hot.end()) {
+    *out = &it->second;
+    return SHIRO_OK;
+  }
+  if (!allocate) return set_error(SHIRO_ERR_CAPTURING, "spmm: LDS rows of the tuning not prepared before capture");
+  if (kernel == SHIRO_KERNEL_SPMM_T && !plan->tr.built) SHIRO_TRY(build_transposed(plan, s));
+  const int64_t nnz = plan->nnz;
+  const int32_t* src = kernel == SHIRO_KERNEL_SPMM ? plan->colmap : plan->tr.row;
+  const int64_t nx = kernel == SHIRO_KERNEL_SPMM ? plan->U : plan->rows;
+  std::vector<int32_t> h((size_t)std::max<int64_t>(nnz, 1));
+  if (nnz > 0) SHIRO_HIP(hipMemcpyAsync(h.data(), src, (size_t)nnz * 4, hipMemcpyDeviceToHost, s));
+  SHIRO_HIP(hipStreamSynchronize(s));
+  // the H most referenced rows (count descending, index ascending)
+  std::vector<int64_t> cnt((size_t)std::max<int64_t>(nx, 1), 0);
+  for (int64_t k = 0; k < nnz; ++k) ++cnt[(size_t)h[k]];
+  std::vector<int32_t> order((size_t)nx);
+  for (int64_t x = 0; x < nx; ++x) order[(size_t)x] = (int32_t)x;
+  const int64_t take = std::min<int64_t>(H, nx);
+  std::partial_sort(order.begin(), order.begin() + take, order.end(), [&](int32_t a, int32_t b) {
+    return cnt[(size_t)a] != cnt[(size_t)b] ? cnt[(size_t)a] > cnt[(size_t)b] : a < b;
+  });
+  int32_t n_hot = 0;
+  while (n_hot < take && cnt[(size_t)order[(size_t)n_hot]] > 1) ++n_hot;  // a row read once gains nothing
+  std::vector<int32_t> slot((size_t)std::max<int64_t>(nx, 1), -1);
+  for (int32_t q = 0; q < n_hot; ++q) slot[(size_t)order[(size_t)q]] = q;
+  for (int64_t k = 0; k < nnz; ++k)
+    if (slot[(size_t)h[k]] >= 0) h[k] = -(slot[(size_t)h[k]] + 1);
+  HotRows hr;
+  hr.H = n_hot;
+  SHIRO_TRY(dev_alloc_n(&hr.walk_idx, std::max<int64_t>(nnz, 1)));
+  SHIRO_TRY(dev_alloc_n(&hr.hot_src, std::max<int32_t>(n_hot, 1)));
+  if (nnz > 0) SHIRO_HIP(hipMemcpyAsync(hr.walk_idx, h.data(), (size_t)nnz * 4, hipMemcpyHostToDevice, s));
+  if (n_hot > 0) SHIRO_HIP(hipMemcpyAsync(hr.hot_src, order.data(), (size_t)n_hot * 4, hipMemcpyHostToDevice, s));
+  SHIRO_HIP(hipStreamSynchronize(s));
+  *out = &(plan->hot[key] = hr);
+  return SHIRO_OK;
+}
+
 int ensure_row_rid(shiro_plan plan, bool allocate, hipStream_t s) {
   if (plan->row_rid) return SHIRO_OK;
   if (!allocate) return set_error(SHIRO_ERR_CAPTURING, "spmm: row ids for the nonzero walk not prepared before capture");
@@ -1683,10 +1761,13 @@ int launch_spmm(shiro_plan plan, const shiro_tuning_t& t, const float* vals, con
   SHIRO_TRY(ensure_rows_work(plan, t.chunk, !stream_capturing(s), s, &wl));
   if (t.group_rows >= 2) SHIRO_TRY(ensure_row_rid(plan, !stream_capturing(s), s));
   SHIRO_TRY(ensure_carry(plan, (int64_t)wl->W * 2 * N, !stream_capturing(s)));
+  const HotRows* hot = nullptr;
+  if (t.group_rows == 3 && t.lds_rows > 0)
+    SHIRO_TRY(ensure_hot(plan, SHIRO_KERNEL_SPMM, t.lds_rows, !stream_capturing(s), s, &hot));
   const float* v = plan_values(plan, vals, s);
   SHIRO_LAUNCH_CHECK();
   return launch_pattern(plan, t, wl, plan->row_ptr, plan->colmap, v, plan->rows, X, ldx, N, in_dt, Y, ldy,
-                        out_dt, s, nullptr, t.group_rows >= 2 ? plan->row_rid : nullptr);
+                        out_dt, s, nullptr, t.group_rows >= 2 ? plan->row_rid : nullptr, nullptr, hot);
 }
 
 int launch_spmm_fixed(shiro_plan plan, const shiro_tuning_t& t, const float* vals, const void* X,
@@ -1703,10 +1784,17 @@ int launch_spmm_fixed(shiro_plan plan, const shiro_tuning_t& t, const float* val
     return set_error(SHIRO_ERR_WORKSPACE,
                      "spmm_noalloc: the carry slots need " + std::to_string(need * 4) +
                          " bytes, more than the fixed work area of " + std::to_string(carry_cap * 4) + " bytes");
+  const HotRows* hot = nullptr;
+  if (t.group_rows == 3 && t.lds_rows > 0) {
+    auto ht = plan->hot.find(std::make_pair((int32_t)SHIRO_KERNEL_SPMM, t.lds_rows));
+    if (ht == plan->hot.end())
+      return set_error(SHIRO_ERR_NOT_READY, "spmm_noalloc: LDS rows of the tuning not built; run shiro_prepare first");
+    hot = &ht->second;
+  }
   const float* v = plan_values(plan, vals, s);
   SHIRO_LAUNCH_CHECK();
   return launch_pattern(plan, t, wl, plan->row_ptr, plan->colmap, v, plan->rows, X, ldx, N, in_dt, Y, ldy,
-                        out_dt, s, nullptr, t.group_rows >= 2 ? plan->row_rid : nullptr, carry);
+                        out_dt, s, nullptr, t.group_rows >= 2 ? plan->row_rid : nullptr, carry, hot);
 }
 
 int build_rowbased(shiro_plan plan, hipStream_t s) {
@@ -1807,9 +1895,14 @@ int launch_spmm_t(shiro_plan plan, const shiro_tuning_t& t, const float* vals, c
   k_gather_vals<<<grid_for(plan->nnz), kBlock, 0, s>>>(plan->tr.perm, vals + plan->nz_begin, plan->nnz,
                                                         plan->tvals);
   SHIRO_LAUNCH_CHECK();
+  const HotRows* hot = nullptr;
+  if (t.group_rows == 3 && t.lds_rows > 0)
+    SHIRO_TRY(ensure_hot(plan, SHIRO_KERNEL_SPMM_T, t.lds_rows, !cap, s, &hot));
   SpmmArgs a{};
   a.ptr = plan->tr.ptr;
-  a.idx = plan->tr.row;
+  a.idx = hot ? hot->walk_idx : plan->tr.row;
+  a.hot_src = hot ? hot->hot_src : nullptr;
+  a.n_hot = hot ? hot->H : 0;
   a.rid = plan->tr.rid;
   a.vals = plan->tvals;
   a.X = dY;
@@ -1962,6 +2055,7 @@ int launch_spmm_per_block(shiro_plan plan, const float* vals, const void* X, int
   }
   shiro_tuning_t t = tuning_for(plan, SHIRO_KERNEL_SPMM, N, in_dt);
   if (t.group_rows < 2) t.group_rows = 2;  // the walk: every block's entries are non-empty rows
+  t.lds_rows = 0;                          // the blocks index Bpacked through their own copies
   const auto& off = plan->seg.h_off;
   for (int32_t q = 0; q < plan->P; ++q) {
     const WorkList& wl = pb.work[q];

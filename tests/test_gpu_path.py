@@ -410,6 +410,46 @@ def test_allocator_failure_reports_oom(shiro):
     assert U == len(oracle.select(oracle.Csr.from_synth(A))[0])
 
 
+@pytest.mark.parametrize("H", [1, 5, 64])
+def test_lds_rows_bit_exact(shiro, run, H):
+    """The windowed walk with its H most referenced gathered rows in LDS
+    (knob lds_rows): forward, and backward with dB rows and fused dvals, in
+    float32 and bfloat16, bit-identical to the same walk reading every row
+    from memory, and within tolerance of the oracle."""
+    dev = run.dev
+    N = run.N
+    dY = run.G.to(dev)
+    for dt in (torch.float32, torch.bfloat16):
+        saved = {k: shiro.get_tuning(run.plan, k, N, dt) for k in ("spmm", "spmm_t")}
+        outs = []
+        try:
+            for lds in (0, H):
+                for k in ("spmm", "spmm_t"):
+                    shiro.set_tuning(run.plan, k, N, dt, chunk=64, lanes=32, unroll=2, group_rows=3, lds_rows=lds)
+                Bp = shiro.pack_B(run.plan, run.B.to(dt).to(dev))
+                Y = shiro.spmm(run.plan, run.Ad.vals, Bp)
+                dB = torch.zeros(run.A.n_cols, N, dtype=dt, device=dev)
+                dvals = torch.zeros(run.A.nnz, device=dev)
+                shiro.spmm_backward(run.plan, run.Ad.vals, dY.to(dt), Bp, dB=dB, dvals=dvals, dB_overwrite=True)
+                torch.cuda.synchronize()
+                outs.append((Y, dB, dvals))
+        finally:
+            for k, t in saved.items():
+                shiro.set_tuning(run.plan, k, N, dt, **t)
+        view = torch.int16 if dt == torch.bfloat16 else torch.int32
+        for a, b in zip(*outs):
+            assert torch.equal(a.view(view) if a.dtype == dt else a, b.view(view) if b.dtype == dt else b)
+        if dt == torch.float32:
+            Yref, Yden = _fwd_ref(run, run.B.numpy())
+            assert oracle.rel_err(outs[1][0].cpu().numpy(), Yref, Yden) <= TOL_F32
+    with pytest.raises(shiro.ShiroError) as e:  # only the windowed walk keeps rows in LDS
+        shiro.set_tuning(run.plan, "spmm", N, group_rows=2, lds_rows=4)
+    assert e.value.name == "INVALID_ARG"
+    with pytest.raises(shiro.ShiroError) as e:
+        shiro.set_tuning(run.plan, "partial_c", N, group_rows=3, lds_rows=4)
+    assert e.value.name == "INVALID_ARG"
+
+
 def test_graph_replays_match_eager(shiro):
     """A captured select+pack+spmm+backward graph, replayed several times with
     eager work in between, gives bit-identical results to the eager calls."""

@@ -120,7 +120,7 @@ def random_tuning(rng, walk=True):
 def test_random_shapes_random_tunings(shiro, seed):
     """Random shapes with a random launch configuration per kernel family
     (chunk sizes that are not powers of two, every lane width, depth and
-    layout, XCD remap, one to sixteen workgroups per CU)."""
+    layout, XCD remap, one to sixteen workgroups per CU, rows in LDS)."""
     A, N, rng = random_case(seed)
     dtype = torch.float32 if seed % 2 == 0 else torch.bfloat16
     tol = TOL_F32 if dtype == torch.float32 else TOL_BF16
@@ -131,6 +131,9 @@ def test_random_shapes_random_tunings(shiro, seed):
     U, _ = shiro.select_rows(plan)
     uc, off, cm = oracle.select(Ac)
     knobs = {k: random_tuning(rng, walk=k != "sddmm") for k in ("spmm", "spmm_t", "sddmm", "partial_c", "aggregate_c")}
+    for k in ("spmm", "spmm_t"):  # rows kept in LDS by the windowed walk
+        if knobs[k]["group_rows"] == 3:
+            knobs[k]["lds_rows"] = int(rng.choice([0, 1, 7, 64]))
     for k, t in knobs.items():
         shiro.set_tuning(plan, k, N, dtype, **t)
         if k in ("partial_c", "aggregate_c"):
