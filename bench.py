@@ -242,6 +242,10 @@ def main():
     roofline = {"bound": "hbm", "kernel": f"{dom} ({kernels_of[dom]})", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes": int(alg[dom]), "duration_us": round(kern_us[dom], 2)}
+    if traffic:
+        # the rate at which the op moves the bytes the counters saw, beside the
+        # device-copy rate measured in the same run (copy_GBs)
+        roofline["traffic_rate_GBs"] = round(traffic / (kern_us[dom] * 1e-6) / 1e9, 1)
 
     out = {
         "metric": "local SpMM GFLOP/s & % HBM peak; BF16/batched/fwd+bwd vs plain FP32",
