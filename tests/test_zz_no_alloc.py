@@ -87,9 +87,26 @@ def test_noalloc_matches_spmm_two_calls(lib):
 def test_noalloc_bf16_and_row_kernels(lib):
     s = lib
     A = synth.small_rmat(12, 8, P=4, p=1)
-    for grp in (0, 1, 2):
+    for grp in (0, 1, 2, 3):
         p = _setup(s, A, 128, torch.bfloat16, tuning={"chunk": 64, "group_rows": grp})
         _check_against_spmm_and_oracle(s, A, *p, torch.bfloat16)
+
+
+def test_noalloc_windowed_walk_lds_rows(lib):
+    s = lib
+    A = synth.small_rmat(13, 16, P=4, p=0)
+    for H in (0, 16):
+        p = _setup(s, A, 128, torch.float32, tuning={"chunk": 64, "group_rows": 3, "lds_rows": H})
+        _check_against_spmm_and_oracle(s, A, *p, torch.float32)
+    # LDS rows of a size the plan has not prepared: refused before any launch
+    plan, Ad, B, Bp = p
+    s.set_tuning(plan, "spmm", 128, torch.float32, chunk=64, group_rows=3, lds_rows=32)
+    Y = torch.full((plan.info()["rows"], 128), 7.0, device=Bp.device)
+    assert _call_noalloc(s, plan, Ad.vals, Bp, Y) == -6
+    torch.cuda.synchronize()
+    assert bool((Y == 7.0).all())
+    s.prepare(plan, 128, torch.float32, ops=("spmm",))
+    _check_against_spmm_and_oracle(s, A, plan, Ad, B, Bp, torch.float32)
 
 
 def test_noalloc_not_prepared_and_too_large(lib):
