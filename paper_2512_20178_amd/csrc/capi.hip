@@ -466,10 +466,11 @@ static int tune_one(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt, Tune
   };
   shiro_tuning_t best = default_tuning(kernel, N, dt);
   float best_ms = 1e30f;
-  auto consider = [&](shiro_tuning_t t) -> int {
+  auto consider = [&](shiro_tuning_t t, float* ms_out = nullptr) -> int {
     float ms;
     int rc = time_candidate(s, [&] { return run(t); }, &ms);
     if (rc != SHIRO_OK) return rc;
+    if (ms_out) *ms_out = ms;
     if (ms < best_ms) {
       best_ms = ms;
       best = t;
@@ -484,10 +485,14 @@ static int tune_one(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt, Tune
       t.unroll = unroll;
       SHIRO_TRY(consider(t));
     }
-  // stage 2: lane width, occupancy, XCD placement around the best
+  // stage 2: kernel form, lane width, occupancy, XCD placement around the
+  // best; the best candidate of each kernel form is kept
   const shiro_tuning_t base = best;
   const bool walk = kernel != SHIRO_KERNEL_SDDMM;
-  for (int grp = 0; grp <= (walk ? 3 : 1); ++grp)
+  const int n_forms = walk ? 4 : 2;
+  float form_ms[4] = {1e30f, 1e30f, 1e30f, 1e30f};
+  shiro_tuning_t form_best[4] = {base, base, base, base};
+  for (int grp = 0; grp < n_forms; ++grp)
     for (int lanes : {64, 32, 16})
       for (int wg : {2, 4, 8, 16})
         for (int xcd : {0, 1}) {
@@ -496,33 +501,56 @@ static int tune_one(shiro_plan plan, int kernel, int32_t N, shiro_dtype dt, Tune
           t.lanes = lanes;
           t.wg_per_cu = wg;
           t.xcd_remap = xcd;
-          SHIRO_TRY(consider(t));
+          float ms = 1e30f;
+          SHIRO_TRY(consider(t, &ms));
+          if (ms < form_ms[grp]) {
+            form_ms[grp] = ms;
+            form_best[grp] = t;
+          }
         }
-  // stage 3: work size and depth again around the best layout, plus the
-  // chunk sizes that give every worker of a full persistent grid exactly one
-  // or two chunks (no tail round)
-  const shiro_tuning_t base3 = best;
-  std::vector<int> chunks{64, 128, 256, 512};
-  for (int m : {1, 2}) {
-    const int fit = fit_chunk(plan, kernel, N, dt, base3, m);
-    if (fit > 0 && std::find(chunks.begin(), chunks.end(), fit) == chunks.end()) chunks.push_back(fit);
+  // stages 3 and 4 refine the two fastest kernel forms separately (a form
+  // that loses at the first stage's depth can win at another one)
+  int forms[4] = {0, 1, 2, 3};
+  std::sort(forms, forms + n_forms, [&](int a, int b) { return form_ms[a] < form_ms[b]; });
+  for (int f = 0; f < std::min(n_forms, 2); ++f) {
+    if (form_ms[forms[f]] >= 1e30f) continue;
+    shiro_tuning_t local = form_best[forms[f]];
+    float local_ms = form_ms[forms[f]];
+    auto refine = [&](const shiro_tuning_t& t) -> int {
+      float ms = 1e30f;
+      SHIRO_TRY(consider(t, &ms));
+      if (ms < local_ms) {
+        local_ms = ms;
+        local = t;
+      }
+      return SHIRO_OK;
+    };
+    // stage 3: work size and depth again around the form's best layout, plus
+    // the chunk sizes that give every worker of a full persistent grid
+    // exactly one or two chunks (no tail round)
+    const shiro_tuning_t base3 = local;
+    std::vector<int> chunks{64, 128, 256, 512};
+    for (int m : {1, 2}) {
+      const int fit = fit_chunk(plan, kernel, N, dt, base3, m);
+      if (fit > 0 && std::find(chunks.begin(), chunks.end(), fit) == chunks.end()) chunks.push_back(fit);
+    }
+    for (int chunk : chunks)
+      for (int unroll : {1, 2, 4}) {
+        shiro_tuning_t t = base3;
+        t.chunk = chunk;
+        t.unroll = unroll;
+        SHIRO_TRY(refine(t));
+      }
+    // stage 4: occupancy and fitted chunk together around the form's best
+    const shiro_tuning_t base4 = local;
+    for (int wg : {2, 4, 8, 16})
+      for (int m : {1, 2, 3}) {
+        shiro_tuning_t t = base4;
+        t.wg_per_cu = wg;
+        t.chunk = fit_chunk(plan, kernel, N, dt, t, m);
+        if (t.chunk > 0) SHIRO_TRY(refine(t));
+      }
   }
-  for (int chunk : chunks)
-    for (int unroll : {1, 2, 4}) {
-      shiro_tuning_t t = base3;
-      t.chunk = chunk;
-      t.unroll = unroll;
-      SHIRO_TRY(consider(t));
-    }
-  // stage 4: occupancy and fitted chunk together around the best layout
-  const shiro_tuning_t base4 = best;
-  for (int wg : {2, 4, 8, 16})
-    for (int m : {1, 2, 3}) {
-      shiro_tuning_t t = base4;
-      t.wg_per_cu = wg;
-      t.chunk = fit_chunk(plan, kernel, N, dt, t, m);
-      if (t.chunk > 0) SHIRO_TRY(consider(t));
-    }
   // stage 5: the most referenced rows of the gathered operand in LDS
   // (windowed walk of spmm and spmm_t); rows of at most 1 KB, so 64 fit
   if (best.group_rows == 3 && (kernel == SHIRO_KERNEL_SPMM || kernel == SHIRO_KERNEL_SPMM_T)) {
