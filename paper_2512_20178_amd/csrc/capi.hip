@@ -232,7 +232,7 @@ shiro_tuning_t default_tuning(int kernel, int32_t, shiro_dtype) {
   return t;
 }
 
-int validate_tuning(int kernel, int32_t, shiro_dtype, const shiro_tuning_t& t) {
+int validate_tuning(int kernel, int32_t N, shiro_dtype dt, const shiro_tuning_t& t) {
   if (kernel < 0 || kernel > SHIRO_KERNEL_AGGREGATE_C)
     return set_error(SHIRO_ERR_INVALID_ARG, "tuning: unknown kernel family");
   if (t.chunk < 16 || t.chunk > (1 << 22)) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: chunk outside [16, 2^22]");
@@ -248,6 +248,18 @@ int validate_tuning(int kernel, int32_t, shiro_dtype, const shiro_tuning_t& t) {
   if (t.lds_rows < 0 || t.lds_rows > 128) return set_error(SHIRO_ERR_INVALID_ARG, "tuning: lds_rows outside [0, 128]");
   if (t.lds_rows > 0 && (t.group_rows != 3 || (kernel != SHIRO_KERNEL_SPMM && kernel != SHIRO_KERNEL_SPMM_T)))
     return set_error(SHIRO_ERR_INVALID_ARG, "tuning: lds_rows needs the windowed walk (group_rows 3) of spmm or spmm_t");
+  if (t.lds_rows > 0 && N > 0) {
+    // one workgroup holds lds_rows rows of its column tile; the fused
+    // backward runs one tile of up to 64 lanes whatever t.lanes says
+    const int vec16 = dt == SHIRO_F32 ? 4 : 8;
+    const int vec = (N % vec16 == 0) ? vec16 : 1;
+    const int64_t need = ceil_div((int64_t)N, (int64_t)vec);  // lanes a tile needs, as the launch sizes it
+    int lanes = kernel == SHIRO_KERNEL_SPMM_T ? 64 : t.lanes;
+    while (lanes > 8 && lanes / 2 >= need) lanes /= 2;
+    const int64_t bytes = (int64_t)t.lds_rows * lanes * vec * (dt == SHIRO_F32 ? 4 : 2);
+    if (bytes > 65536)
+      return set_error(SHIRO_ERR_INVALID_ARG, "tuning: lds_rows rows of this width exceed 64 KB of LDS");
+  }
   return SHIRO_OK;
 }
 

@@ -1733,11 +1733,23 @@ int ensure_hot(shiro_plan plan, int kernel, int32_t H, bool allocate, hipStream_
     if (slot[(size_t)h[k]] >= 0) h[k] = -(slot[(size_t)h[k]] + 1);
   HotRows hr;
   hr.H = n_hot;
-  SHIRO_TRY(dev_alloc_n(&hr.walk_idx, std::max<int64_t>(nnz, 1)));
-  SHIRO_TRY(dev_alloc_n(&hr.hot_src, std::max<int32_t>(n_hot, 1)));
-  if (nnz > 0) SHIRO_HIP(hipMemcpyAsync(hr.walk_idx, h.data(), (size_t)nnz * 4, hipMemcpyHostToDevice, s));
-  if (n_hot > 0) SHIRO_HIP(hipMemcpyAsync(hr.hot_src, order.data(), (size_t)n_hot * 4, hipMemcpyHostToDevice, s));
-  SHIRO_HIP(hipStreamSynchronize(s));
+  // nothing is kept unless every step succeeds
+  auto fail = [&](int rc) {
+    dev_free(hr.walk_idx);
+    dev_free(hr.hot_src);
+    return rc;
+  };
+  int rc = dev_alloc_n(&hr.walk_idx, std::max<int64_t>(nnz, 1));
+  if (rc == SHIRO_OK) rc = dev_alloc_n(&hr.hot_src, std::max<int32_t>(n_hot, 1));
+  if (rc != SHIRO_OK) return fail(rc);
+  hipError_t e = hipSuccess;
+  if (nnz > 0) e = hipMemcpyAsync(hr.walk_idx, h.data(), (size_t)nnz * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && n_hot > 0)
+    e = hipMemcpyAsync(hr.hot_src, order.data(), (size_t)n_hot * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess)
+    return fail(set_error(e == hipErrorOutOfMemory ? SHIRO_ERR_OOM : SHIRO_ERR_HIP,
+                          std::string("LDS rows: ") + hipGetErrorString(e)));
   *out = &(plan->hot[key] = hr);
   return SHIRO_OK;
 }

@@ -448,6 +448,12 @@ def test_lds_rows_bit_exact(shiro, run, H):
     with pytest.raises(shiro.ShiroError) as e:
         shiro.set_tuning(run.plan, "partial_c", N, group_rows=3, lds_rows=4)
     assert e.value.name == "INVALID_ARG"
+    # 128 FP32 rows of a 64-lane tile (1 KB each) would need 128 KB of LDS;
+    # 64 of them fit the 64 KB a workgroup may take
+    with pytest.raises(shiro.ShiroError) as e:
+        shiro.set_tuning(run.plan, "spmm", 256, torch.float32, lanes=64, group_rows=3, lds_rows=128)
+    assert e.value.name == "INVALID_ARG" and "64 KB" in str(e.value)
+    shiro.set_tuning(run.plan, "spmm", 256, torch.float32, lanes=64, group_rows=3, lds_rows=64)
 
 
 def test_graph_replays_match_eager(shiro):
@@ -790,6 +796,52 @@ def test_subset_plan_backward(shiro, run):
     fden = oracle.sddmm(Ac, run.G.numpy(), run.B.numpy(), None, abs_mode=True)
     assert oracle.rel_err(dv[keep], full[keep], fden[keep]) <= TOL_F32
     assert bool((dv[~keep] == -5.0).all())  # the row-based nonzeros are not touched
+
+
+def test_lds_rows_setup_failure_frees_its_buffers(shiro):
+    """When the LDS-row setup cannot get its second buffer, the call reports
+    OOM, hands back the buffer it already had, and a later prepare with a
+    working allocator builds the rows (results bit-identical to no LDS rows)."""
+    from paper_2512_20178_amd import _lib
+
+    A, N = make_case("rmat12_P8_p0")
+    dev = torch.device("cuda")
+    Ad = A.to(dev)
+    plan = shiro.partition(Ad.row_ptr, Ad.col, A.n_rows, A.n_cols, A.P, A.p)
+    shiro.select_rows(plan)
+    base = {"chunk": 64, "lanes": 32, "unroll": 2, "group_rows": 3, "lds_rows": 0}
+    shiro.set_tuning(plan, "spmm", N, torch.float32, **base)
+    shiro.prepare(plan, N, torch.float32, ops=("spmm",))
+    B = synth.dense(A.n_cols, N, 0, synth.STREAM_B, device=dev)
+    Bp = shiro.pack_B(plan, B)
+    Y0 = shiro.spmm(plan, Ad.vals, Bp)
+    torch.cuda.synchronize()
+    live = {}
+
+    def _alloc(nbytes, ctx):
+        if nbytes <= 4096:  # the hot-row slot list (a few bytes) is refused
+            return None
+        t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+        live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _free(ptr, nbytes, ctx):
+        live.pop(ptr)
+
+    hooks = (_lib.ALLOC_FN(_alloc), _lib.FREE_FN(_free))
+    shiro.set_tuning(plan, "spmm", N, torch.float32, **dict(base, lds_rows=16))
+    assert shiro._L().shiro_set_allocator(hooks[0], hooks[1], None) == 0
+    try:
+        with pytest.raises(_lib.ShiroError) as e:
+            shiro.prepare(plan, N, torch.float32, ops=("spmm",))
+        assert e.value.name == "OOM"
+        assert not live, "the index copy was not handed back"
+    finally:
+        shiro.use_torch_allocator(False)
+    shiro.prepare(plan, N, torch.float32, ops=("spmm",))
+    Y1 = shiro.spmm(plan, Ad.vals, Bp)
+    torch.cuda.synchronize()
+    assert torch.equal(Y1.view(torch.int32), Y0.view(torch.int32))
 
 
 def test_torch_allocator(shiro):
