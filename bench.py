@@ -236,7 +236,16 @@ def main():
     # the product kernel each op ran, from the plan's tuning (group_rows)
     kname = {0: "k_spmm", 1: "k_spmm_grp", 2: "k_spmm_flat", 3: "k_spmm_win"}
     kf = kname[shiro.get_tuning(plan, "spmm", N, tdt)["group_rows"]]
-    kb = kname[shiro.get_tuning(plan, "spmm_t", N, tdt)["group_rows"]]
+    tb = shiro.get_tuning(plan, "spmm_t", N, tdt)
+    kb = kname[tb["group_rows"]]
+    # the fused FP32 transposed walk with one nonzero per step and lane groups
+    # of 16 or more runs as the 8-wavefronts-per-SIMD build of that walk
+    vec = 4 if N % 4 == 0 else 1
+    lanes = 64
+    while lanes > 8 and lanes // 2 >= -(-N // vec):
+        lanes //= 2
+    if tb["group_rows"] == 3 and tb["unroll"] == 1 and tdt == torch.float32 and lanes >= 16:
+        kb = "k_spmm_win_w8"
     kernels_of = {"pack_B": "k_pack", "spmm": f"{kf} + k_fixup",
                   "backward": f"k_gather_vals + {kb}<dot> + k_fixup + k_scatter_vals"}
     roofline = {"bound": "hbm", "kernel": f"{dom} ({kernels_of[dom]})", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

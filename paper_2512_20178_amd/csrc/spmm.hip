@@ -16,6 +16,7 @@
 // deep, and are reduced with cross-lane shuffles when the row ends.  All row
 // bookkeeping is wavefront-uniform and lives in scalar registers.
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "plan.hpp"
@@ -147,6 +148,10 @@ struct SpmmArgs {
       reinterpret_cast<TOUT*>((a).out), (a).ldo, reinterpret_cast<TOUT*>((a).scat), (a).lds,   \
       (a).scat_idx, (a).chunk_row, (a).chunk_nz, (a).rid, (a).carry, (a).W, (a).R, (a).N,     \
       (a).chunks_per_wave, (a).xcd_remap, (a).scat_mode, (a).hot_src, (a).n_hot
+
+#define SHIRO_SPMM_NAMES                                                                       \
+  ptr, idx, vals, D, ldd, dot_out, X, ldx, out, ldo, scat, lds, scat_idx, chunk_row, chunk_nz, rid, \
+      carry, W, R, N, cpw, xcd_remap, scat_mode, hot_src, n_hot
 
 template <typename TOUT, int VEC>
 __device__ __forceinline__ void epilogue_row(TOUT* __restrict__ out, int64_t ldo, TOUT* __restrict__ scat,
@@ -640,7 +645,7 @@ __device__ __forceinline__ T lane_pull(int src_lane, T v) {
 }
 
 template <typename TIN, typename TOUT, int LANES, int VEC, int UNROLL, bool DOT, int SCAT>
-__global__ __launch_bounds__(kBlock) void k_spmm_win(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
+__device__ __forceinline__ void spmm_win_body(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
   constexpr int G = kWave / LANES;
   constexpr int WIN = LANES;          // nonzeros per window and lane group
   constexpr int WS = WIN / UNROLL;    // steps per window
@@ -838,6 +843,26 @@ __global__ __launch_bounds__(kBlock) void k_spmm_win(SHIRO_SPMM_PARAMS(TIN, TOUT
     if (cur >= 0) flush();
     zero_rows(row_end);
   }
+}
+
+template <typename TIN, typename TOUT, int LANES, int VEC, int UNROLL, bool DOT, int SCAT>
+__global__ __launch_bounds__(kBlock) void k_spmm_win(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
+  spmm_win_body<TIN, TOUT, LANES, VEC, UNROLL, DOT, SCAT>(SHIRO_SPMM_NAMES);
+}
+
+// The same walk compiled for eight wavefronts per SIMD (at most 64 VGPRs; a
+// few values spill).  The fused transposed product in FP32 with one nonzero
+// per step and lane groups of 16 or more has short rows (a few nonzeros per
+// packed column), so its waves spend most of their time waiting on loads and
+// more of them in flight pay: on the 2^24 R-MAT panel 516 -> 503 us at
+// N = 128 and 331 -> 326 us at N = 64, results bit-identical.  With 8-lane
+// groups (N = 32) the spills cost more than the extra waves gain (243 -> 248
+// us), and the forward walks lose to the spills too, so they keep the
+// default budget.
+template <typename TIN, typename TOUT, int LANES, int VEC, int UNROLL, bool DOT, int SCAT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_spmm_win_w8(
+    SHIRO_SPMM_PARAMS(TIN, TOUT)) {
+  spmm_win_body<TIN, TOUT, LANES, VEC, UNROLL, DOT, SCAT>(SHIRO_SPMM_NAMES);
 }
 
 // Rows cut by chunk boundaries.  split[3 i] = first chunk ws, split[3 i + 1]
@@ -1318,10 +1343,15 @@ template <typename TIN, typename TOUT, int VEC, bool DOT, int SCAT>
 int spmm_dispatch(const shiro_tuning_t& t, dim3 grid, hipStream_t s, const SpmmArgs& a) {
 #define SHIRO_SPMM_CASE(L, U)                                                                          \
   if (t.lanes == L && t.unroll == U) {                                                                 \
-    if (t.group_rows == 3 && a.rid)                                                                    \
-      k_spmm_win<TIN, TOUT, L, VEC, U, DOT, SCAT><<<grid, kBlock, (size_t)a.n_hot * L * VEC * sizeof(TIN), s>>>( \
-          SHIRO_SPMM_ARGS(TIN, TOUT, a));                                                             \
-    else if (t.group_rows == 2 && a.rid)                                                               \
+    if (t.group_rows == 3 && a.rid) {                                                                  \
+      const size_t lds_bytes = (size_t)a.n_hot * L * VEC * sizeof(TIN);                               \
+      if constexpr (DOT && U == 1 && L >= 16 && std::is_same<TIN, float>::value)                      \
+        k_spmm_win_w8<TIN, TOUT, L, VEC, U, DOT, SCAT><<<grid, kBlock, lds_bytes, s>>>(                \
+            SHIRO_SPMM_ARGS(TIN, TOUT, a));                                                           \
+      else                                                                                             \
+        k_spmm_win<TIN, TOUT, L, VEC, U, DOT, SCAT><<<grid, kBlock, lds_bytes, s>>>(                   \
+            SHIRO_SPMM_ARGS(TIN, TOUT, a));                                                           \
+    } else if (t.group_rows == 2 && a.rid)                                                               \
       k_spmm_flat<TIN, TOUT, L, VEC, U, DOT, SCAT><<<grid, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a)); \
     else if (t.group_rows)                                                                             \
       k_spmm_grp<TIN, TOUT, L, VEC, U, DOT, SCAT><<<grid, kBlock, 0, s>>>(SHIRO_SPMM_ARGS(TIN, TOUT, a)); \
