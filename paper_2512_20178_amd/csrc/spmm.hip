@@ -654,9 +654,9 @@ __device__ __forceinline__ void spmm_win_body(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
   const int g = lane / LANES;
   const int li = lane % LANES;
   const int base_lane = g * LANES;
-  const int64_t c = (int64_t)blockIdx.y * (LANES * VEC) + (int64_t)li * VEC;
+  const int32_t c = (int32_t)blockIdx.y * (LANES * VEC) + li * VEC;  // below N
   const bool cvalid = c < N;
-  const int64_t cl = cvalid ? c : 0;
+  const int32_t cl = cvalid ? c : 0;
 
   // hot rows: slot h holds the tile's LANES*VEC elements of X row hot_src[h]
   extern __shared__ __align__(16) unsigned char hot_lds[];
@@ -686,13 +686,15 @@ __device__ __forceinline__ void spmm_win_body(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
     const bool has_head = j0 > ptr[i0];
     const int32_t row_end = i1 < R ? i1 : R;
     int32_t next = has_head ? i0 + 1 : i0;
-    float* const head_slot = carry + (w * 2) * N + c;
-    float* const tail_slot = carry + (w * 2 + 1) * N + c;
+    // carry slots of this chunk, addressed where used (at its ends only), so
+    // that no registers hold them through the walk
+    auto head_slot = [&]() { return carry + (w * 2) * N + c; };
+    auto tail_slot = [&]() { return carry + (w * 2 + 1) * N + c; };
     if (has_head && ptr[i0 + 1] <= j0 && cvalid) {  // row i0 holds nothing here
       float z[VEC];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) z[e] = 0.f;
-      Elem<float>::template store<VEC>(head_slot, z);
+      Elem<float>::template store<VEC>(head_slot(), z);
     }
     auto put = [&](int32_t r, int32_t sidx, const float(&a)[VEC], bool zero) {
       if (out) Elem<TOUT>::template store_nt<VEC>(out + (int64_t)r * ldo + c, a);
@@ -723,8 +725,8 @@ __device__ __forceinline__ void spmm_win_body(SHIRO_SPMM_PARAMS(TIN, TOUT)) {
     for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
     auto flush = [&]() {
       if (!cvalid) return;
-      if (cur == i0 && has_head) Elem<float>::template store<VEC>(head_slot, acc);
-      else if (cur == i1) Elem<float>::template store<VEC>(tail_slot, acc);
+      if (cur == i0 && has_head) Elem<float>::template store<VEC>(head_slot(), acc);
+      else if (cur == i1) Elem<float>::template store<VEC>(tail_slot(), acc);
       else put(cur, scur, acc, false);
     };
     if (j0 < j1) {
