@@ -410,6 +410,37 @@ def test_allocator_failure_reports_oom(shiro):
     assert U == len(oracle.select(oracle.Csr.from_synth(A))[0])
 
 
+def test_backward_walk_builds_bit_exact(shiro, run):
+    """The fused float32 transposed walk with one nonzero per step runs from
+    the build compiled for eight wavefronts per SIMD (lane groups of 16 or
+    more); with two per step it runs from the default build.  Both keep each
+    packed column's sum in nonzero order over the same chunks, so dBpacked and
+    the value gradients are bit-identical, and within tolerance of the oracle."""
+    dev = run.dev
+    N = run.N
+    dt = torch.float32
+    saved = shiro.get_tuning(run.plan, "spmm_t", N, dt)
+    Bp = shiro.pack_B(run.plan, run.B.to(dev))
+    dY = run.G.to(dev)
+    outs = []
+    try:
+        for unroll in (1, 2):
+            shiro.set_tuning(run.plan, "spmm_t", N, dt, chunk=64, lanes=32, unroll=unroll, group_rows=3, lds_rows=0)
+            dBp = torch.full((run.U, N), float("nan"), device=dev)
+            dvals = torch.zeros(run.A.nnz, device=dev)
+            shiro.spmm_backward(run.plan, run.Ad.vals, dY, Bp, dBpacked=dBp, dvals=dvals)
+            torch.cuda.synchronize()
+            outs.append((dBp, dvals))
+    finally:
+        shiro.set_tuning(run.plan, "spmm_t", N, dt, **saved)
+    for a, b in zip(*outs):
+        assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+    rdBp, rden, rdv, rdv_den = _bwd_refs(run, run.B.numpy(), run.G.numpy())
+    assert oracle.rel_err(outs[0][0].cpu().numpy(), rdBp, rden) <= TOL_F32
+    gv = outs[0][1].cpu().numpy()[run.Ac.nz_begin:run.Ac.nz_begin + run.Ac.nnz_panel]
+    assert oracle.rel_err(gv, rdv, rdv_den) <= TOL_F32
+
+
 @pytest.mark.parametrize("H", [1, 5, 64])
 def test_lds_rows_bit_exact(shiro, run, H):
     """The windowed walk with its H most referenced gathered rows in LDS
