@@ -1637,12 +1637,14 @@ int launch_pack(shiro_plan plan, const void* B, int64_t ldb, int32_t N, shiro_dt
   // Four workgroups per CU: on the 2^24 R-MAT panel (FP32, N = 128) 2, 4, 8
   // and 16 gave 315, 246, 261 and 270 us -- fewer random rows of the large B
   // in flight at once run faster, down to the point where latency shows.
+  // Eight rows per lane group per round: 2, 4 and 8 gave 255, 246 and 242 us
+  // (BF16 134, 129 and 124 us; the ER panel 764, 722 and 722 us).
   const unsigned nb = grid_for(U * 8, (int64_t)plan->num_cus * 4);
   if (dt == SHIRO_F32) {
     const int v = vec_for<float>(N, {{B, ldb}, {Bp, ldp}});
     const int64_t lanes = effective_lanes(64, N, v);
     auto go = [&](auto L, auto V) {
-      k_pack<float, decltype(L)::value, decltype(V)::value, 4><<<nb, kBlock, 0, s>>>(
+      k_pack<float, decltype(L)::value, decltype(V)::value, 8><<<nb, kBlock, 0, s>>>(
           plan->unique_cols, U, (const float*)B, ldb, (float*)Bp, ldp, N);
     };
     if (v == 4) {
@@ -1657,7 +1659,7 @@ int launch_pack(shiro_plan plan, const void* B, int64_t ldb, int32_t N, shiro_dt
     const int v = vec_for<bf16_t>(N, {{B, ldb}, {Bp, ldp}});
     const int64_t lanes = effective_lanes(64, N, v);
     auto go = [&](auto L, auto V) {
-      k_pack<bf16_t, decltype(L)::value, decltype(V)::value, 4><<<nb, kBlock, 0, s>>>(
+      k_pack<bf16_t, decltype(L)::value, decltype(V)::value, 8><<<nb, kBlock, 0, s>>>(
           plan->unique_cols, U, (const bf16_t*)B, ldb, (bf16_t*)Bp, ldp, N);
     };
     if (v == 8) {
