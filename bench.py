@@ -422,8 +422,65 @@ def main():
         out["cpu_baseline"] = cpu_baseline(A, B, G, N, args, out)
         # error of each output against the FP64 oracle, beside the BF16 speedup
         out["precision"] = precision_report(A, B, G, samples, step_out)
+        if not args.no_extras and args.workload == "rmat24_p128_panel0" and tdt == torch.float32:
+            del B, G
+            torch.cuda.empty_cache()
+            out["precision_form"] = precision_form(shiro, synth, args, dev)
 
     print(json.dumps(out), flush=True)
+
+
+def precision_form(shiro, synth, args, dev):
+    """The precision form on its own matrix: the 2^22 R-MAT (250M nonzeros, one
+    block) at N = 256, the step (select, pack, spmm, backward with dB rows and
+    dvals) with float32 and with bfloat16 storage, the BF16 speedup, and the
+    error of each output against the FP64 oracle on the float32 inputs."""
+    import numpy as np
+    import torch
+
+    A = synth.config4(device=dev)
+    N = 256
+    plan = shiro.partition(A.row_ptr, A.col, A.n_rows, A.n_cols, A.P, A.p)
+    U, _ = shiro.select_rows(plan)
+    info = plan.info()
+    M = info["rows"]
+    B = synth.dense(A.n_cols, N, 0, synth.STREAM_B, device=dev)
+    G = synth.dense(M, N, 0, synth.STREAM_DY, device=dev)
+    smp = sample_outputs(A, info, np, torch)
+    res = {"workload": "rmat22_ef64", "N": N, "nnz": int(A.nnz), "U": int(U)}
+    outs = {}
+    for dt in (torch.float32, torch.bfloat16):
+        if not args.no_autotune:
+            shiro.autotune(plan, N, dt, ops=("spmm", "backward"))
+        shiro.prepare(plan, N, dt, ops=("spmm", "backward"))
+        Bd, Gd = B.to(dt), G.to(dt)
+        Bp = torch.empty(U, N, dtype=dt, device=dev)
+        Y = torch.empty(M, N, dtype=dt, device=dev)
+        dB = torch.zeros(A.n_cols, N, dtype=dt, device=dev)
+        dv = torch.zeros(A.nnz, device=dev)
+
+        def stp():
+            shiro.refresh_selection(plan)
+            shiro.pack_B(plan, Bd, out=Bp)
+            shiro.spmm(plan, A.vals, Bp, out=Y)
+            shiro.spmm_backward(plan, A.vals, Gd, Bp, dB=dB, dvals=dv, dB_overwrite=True)
+
+        stp()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(3):
+            stp()
+        b.record()
+        torch.cuda.synchronize()
+        res["bf16_step_us" if dt == torch.bfloat16 else "f32_step_us"] = round(a.elapsed_time(b) / 3 * 1e3, 1)
+        outs[dt] = take_samples(smp, Y, dB, dv)
+        del Bd, Gd, Bp, Y, dB, dv
+        torch.cuda.empty_cache()
+    res["bf16_speedup"] = round(res["f32_step_us"] / res["bf16_step_us"], 3)
+    res["precision"] = precision_report(A, B, G, smp, outs)
+    log(f"precision form: {res}")
+    return res
 
 
 def n_sweep(shiro, synth, plan, A, vals, U, M, tdt, dev, timed, args):
