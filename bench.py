@@ -426,6 +426,7 @@ def main():
             del B, G
             torch.cuda.empty_cache()
             out["precision_form"] = precision_form(shiro, synth, args, dev)
+            out["differentiation_form"] = differentiation_form(shiro, synth, args, dev)
 
     print(json.dumps(out), flush=True)
 
@@ -480,6 +481,73 @@ def precision_form(shiro, synth, args, dev):
     res["bf16_speedup"] = round(res["f32_step_us"] / res["bf16_step_us"], 3)
     res["precision"] = precision_report(A, B, G, smp, outs)
     log(f"precision form: {res}")
+    return res
+
+
+def differentiation_form(shiro, synth, args, dev):
+    """The differentiation form on its own matrix: the GCN layer (symmetrised,
+    normalised 2^21 R-MAT, N = 128) through the autograd Function, forward and
+    backward (dB and dvals), timed as autograd runs it (it allocates and
+    zero-fills the gradients) and as library calls, with the error of Y, dB
+    and dvals against the FP64 oracle on sampled outputs."""
+    import numpy as np
+    import torch
+
+    A = synth.config5(device=dev)
+    N = 128
+    plan = shiro.partition(A.row_ptr, A.col, A.n_rows, A.n_cols, A.P, A.p)
+    U, _ = shiro.select_rows(plan)
+    info = plan.info()
+    M = info["rows"]
+    if not args.no_autotune:
+        shiro.autotune(plan, N, torch.float32, ops=("spmm", "backward"))
+    shiro.prepare(plan, N, torch.float32, ops=("spmm", "backward"))
+    B = synth.dense(A.n_cols, N, 0, synth.STREAM_B, device=dev)
+    G = synth.dense(M, N, 0, synth.STREAM_DY, device=dev)
+    smp = sample_outputs(A, info, np, torch)
+    vp = A.vals.clone().requires_grad_(True)
+    Bg = B.clone().requires_grad_(True)
+    res = {"workload": "gcn_rmat21_ef25", "N": N, "nnz": int(A.nnz), "U": int(U)}
+
+    def autograd_step():
+        vp.grad = None
+        Bg.grad = None
+        Y = shiro.shiro_spmm(plan, vp, Bg)
+        Y.backward(G)
+        return Y
+
+    def timed(fn, n=3):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(n):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return round(a.elapsed_time(b) / n * 1e3, 1)
+
+    res["autograd_step_us"] = timed(autograd_step)
+    Y = autograd_step()
+    torch.cuda.synchronize()
+    samples = take_samples(smp, Y.detach(), Bg.grad, vp.grad)
+    del Y
+    Bp = torch.empty(U, N, device=dev)
+    Yl = torch.empty(M, N, device=dev)
+    dB = torch.zeros(A.n_cols, N, device=dev)
+    dv = torch.zeros(A.nnz, device=dev)
+
+    def library_step():
+        shiro.refresh_selection(plan)
+        shiro.pack_B(plan, B, out=Bp)
+        shiro.spmm(plan, A.vals, Bp, out=Yl)
+        shiro.spmm_backward(plan, A.vals, G, Bp, dB=dB, dvals=dv, dB_overwrite=True)
+
+    res["library_step_us"] = timed(library_step)
+    del Bp, Yl, dB, dv, vp, Bg
+    torch.cuda.empty_cache()
+    res["precision"] = precision_report(A, B, G, smp, {torch.float32: samples})
+    log(f"differentiation form: {res}")
     return res
 
 
