@@ -405,6 +405,16 @@ def main():
             del Y32
         if args.workload in ("rmat24_p128_panel0", "er24_p128_panel0") and args.N is None:
             out["n_sweep"] = n_sweep(shiro, synth, plan, A, vals, U, M, tdt, dev, timed, args)
+        if args.workload == "rmat24_p128_panel0" and args.N is None:
+            # the batched form's contrast case: the Erdos-Renyi panel, whose
+            # blocks are all about the same size
+            Ae = synth.config3_er(device=dev)
+            pe = shiro.partition(Ae.row_ptr, Ae.col, Ae.n_rows, Ae.n_cols, Ae.P, Ae.p)
+            Ue, _ = shiro.select_rows(pe)
+            out["n_sweep_er24_p128_panel0"] = n_sweep(shiro, synth, pe, Ae, Ae.vals, Ue, pe.info()["rows"], tdt, dev,
+                                                      timed, args)
+            del pe, Ae
+            torch.cuda.empty_cache()
         # the same layer through the autograd Function (allocates and zero-fills
         # dB and dvals on every backward, as autograd does)
         vp = vals.detach().clone().requires_grad_(True)
