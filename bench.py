@@ -437,6 +437,7 @@ def main():
             torch.cuda.empty_cache()
             out["precision_form"] = precision_form(shiro, synth, args, dev)
             out["differentiation_form"] = differentiation_form(shiro, synth, args, dev)
+            out["plain_form"] = plain_form(shiro, synth, args, dev)
 
     print(json.dumps(out), flush=True)
 
@@ -491,6 +492,56 @@ def precision_form(shiro, synth, args, dev):
     res["bf16_speedup"] = round(res["f32_step_us"] / res["bf16_step_us"], 3)
     res["precision"] = precision_report(A, B, G, smp, outs)
     log(f"precision form: {res}")
+    return res
+
+
+def plain_form(shiro, synth, args, dev):
+    """The plain single-block case: the 4096-vertex R-MAT (one block) at
+    N = 32, the step's time, its selection against the oracle's unique-column
+    set (bit for bit) and the error of each output against the FP64 oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+
+    A = synth.config1(device=dev)
+    N = 32
+    plan = shiro.partition(A.row_ptr, A.col, A.n_rows, A.n_cols, A.P, A.p)
+    U, _ = shiro.select_rows(plan)
+    info = plan.info()
+    M = info["rows"]
+    if not args.no_autotune:
+        shiro.autotune(plan, N, torch.float32, ops=("spmm", "backward"))
+    shiro.prepare(plan, N, torch.float32, ops=("spmm", "backward"))
+    B = synth.dense(A.n_cols, N, 0, synth.STREAM_B, device=dev)
+    G = synth.dense(M, N, 0, synth.STREAM_DY, device=dev)
+    Bp = torch.empty(U, N, device=dev)
+    Y = torch.empty(M, N, device=dev)
+    dB = torch.zeros(A.n_cols, N, device=dev)
+    dv = torch.zeros(A.nnz, device=dev)
+
+    def stp():
+        shiro.refresh_selection(plan)
+        shiro.pack_B(plan, B, out=Bp)
+        shiro.spmm(plan, A.vals, Bp, out=Y)
+        shiro.spmm_backward(plan, A.vals, G, Bp, dB=dB, dvals=dv, dB_overwrite=True)
+
+    stp()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(20):
+        stp()
+    b.record()
+    torch.cuda.synchronize()
+    uc = shiro.selection(plan)[0].cpu().numpy()
+    Ac = oracle.Csr.from_synth(A.to(torch.device("cpu")))
+    smp = sample_outputs(A, info, np, torch)
+    res = {"workload": "rmat12_ef16", "N": N, "nnz": int(A.nnz), "U": int(U),
+           "step_us": round(a.elapsed_time(b) / 20 * 1e3, 1),
+           "unique_cols_match_oracle": bool(np.array_equal(uc, oracle.select(Ac)[0])),
+           "precision": precision_report(A, B, G, smp, {torch.float32: take_samples(smp, Y, dB, dv)})}
+    log(f"plain form: {res}")
     return res
 
 
