@@ -219,7 +219,8 @@ def test_rmat24_walk_matches_row_kernels(shiro, rmat24):
     try:
         for grp in (1, 2):
             for k in ("spmm", "spmm_t"):
-                shiro.set_tuning(plan, k, N, chunk=256, lanes=32, unroll=4, group_rows=grp, xcd_remap=0, wg_per_cu=16)
+                shiro.set_tuning(plan, k, N, chunk=256, lanes=32, unroll=4, group_rows=grp, xcd_remap=0, wg_per_cu=16,
+                                lds_rows=0)
             Y = shiro.spmm(plan, A.vals, Bp)
             dB = torch.zeros(A.n_cols, N, device=dev)
             dv = torch.zeros(A.nnz, device=dev)
